@@ -1,0 +1,97 @@
+"""Planted mistakes in the oracle (CPU only): each must be caught by a pin.
+
+Each mutation patches one piece of the oracle for the duration of a test and shows that the
+two-tetrahedron brute force (or the energy pin) no longer agrees with it.
+"""
+import numpy as np
+import pytest
+
+from oracle import maxwell as W
+from oracle import mesh as Mm
+from oracle import refelem as R
+
+from test_oracle_maxwell import assemble, brute_force_operator, mass_weight
+
+VXYZ = np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.05, 0.9, 0.1], [0.1, 0.0, 1.1],
+                 [0.9, 0.8, 0.95]])
+ETOV = np.array([[0, 1, 2, 3], [1, 2, 3, 4]])
+N = 2
+
+
+@pytest.fixture(scope="module")
+def reference_operator():
+    A_bf, _ = brute_force_operator(VXYZ, Mm.orient(VXYZ, ETOV), N)
+    return A_bf
+
+
+def _mismatch(A_bf):
+    mo = Mm.Mesh(VXYZ, ETOV, R.ref_element(N))
+    A = assemble(mo)
+    return np.linalg.norm(A - A_bf) / np.linalg.norm(A_bf)
+
+
+def test_unmutated_oracle_agrees(reference_operator):
+    assert _mismatch(reference_operator) < 1e-11
+
+
+def _swap_eh_volume(mesh, u):
+    v = ORIG_VOLUME(mesh, u)
+    return np.concatenate([-v[3:], -v[:3]])
+
+
+ORIG_VOLUME = W.volume_term
+ORIG_FLUX = W.surface_flux
+
+
+def _flux_wrong_normal(mesh, u, alpha=1.0, eps=None, mu=None):
+    saved = mesh.n
+    mesh.n = -saved
+    try:
+        return ORIG_FLUX(mesh, u, alpha, eps, mu)
+    finally:
+        mesh.n = saved
+
+
+def _flux_no_neighbour(mesh, u, alpha=1.0, eps=None, mu=None):
+    saved = mesh.vmapP
+    mesh.vmapP = mesh.vmapM
+    try:
+        return ORIG_FLUX(mesh, u, alpha, eps, mu)
+    finally:
+        mesh.vmapP = saved
+
+
+def _flux_half(mesh, u, alpha=1.0, eps=None, mu=None):
+    return 0.5 * ORIG_FLUX(mesh, u, alpha, eps, mu)
+
+
+@pytest.mark.parametrize("name,target,replacement", [
+    ("E/H blocks exchanged in the volume term", "volume_term", _swap_eh_volume),
+    ("normal sign flipped in the flux", "surface_flux", _flux_wrong_normal),
+    ("neighbour trace replaced by own trace", "surface_flux", _flux_no_neighbour),
+    ("flux scaled by 1/2 twice", "surface_flux", _flux_half),
+])
+def test_planted_rhs_mistake_is_caught(monkeypatch, reference_operator, name, target, replacement):
+    monkeypatch.setattr(W, target, replacement)
+    assert _mismatch(reference_operator) > 1e-3, name
+
+
+def test_transposed_derivative_matrix_is_caught(monkeypatch, reference_operator):
+    ref = R.ref_element(N)
+    monkeypatch.setattr(ref, "Dr", ref.Dr.T.copy())
+    assert _mismatch(reference_operator) > 1e-3
+
+
+def test_lift_without_face_mass_is_caught(monkeypatch, reference_operator):
+    ref = R.ref_element(N)
+    monkeypatch.setattr(ref, "LIFT", np.linalg.solve(ref.M, (ref.Emat != 0).astype(float)))
+    assert _mismatch(reference_operator) > 1e-3
+
+
+def test_anti_dissipative_flux_is_caught():
+    v = VXYZ
+    m = Mm.Mesh(v, ETOV, R.ref_element(N))
+    A = assemble(m, alpha=-1.0)
+    Mw = mass_weight(m)
+    S = Mw @ A + A.T @ Mw
+    assert np.max(np.linalg.eigvalsh(S)) > 1e-6 * np.linalg.norm(Mw @ A)
