@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of the nodal DG Maxwell hot path on one MI355X.
+
+Workload: unit cube, 6 * 40^3 = 384,000 tetrahedra with interior vertices jittered by
++-0.15 h (seed 1) and elements randomly permuted (seed 2), order N = 4 (Np = 35), FP32,
+perfectly conducting walls, six random smooth initial fields (seed 3). One step = one
+five-stage low-storage RK4 step, i.e. five evaluations of the full semi-discrete operator
+(volume curl, flux gather with the upwind flux and the wall mirror, lift) each fused with its
+RK update. Timed: --steps steps after --warmup untimed ones, between HIP events on the
+stream the kernels run on, inputs resident in HBM.
+
+Prints one JSON line. `value` is algorithmic GFLOP/s (adds and multiplies, FMA = 2; no
+padding work), the paper's measure of Sec. 6.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG RHS GFLOP/s + HBM GB/s (roofline %); solves/s + p50/p99 latency vs plain"
+HBM_PEAK_GBS = 8000.0
+PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def counts(N):
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    return Np, Nfp
+
+
+def flops_per_elem_stage(N):
+    """Algorithmic flops of one fused stage per element: reference derivatives 36 Np^2,
+    physical combine + curl 66 Np, lift 48 Np Nfp + 6 Np, flux 58 per face node,
+    RK update 5 per value."""
+    Np, Nfp = counts(N)
+    return 36 * Np * Np + 66 * Np + 48 * Np * Nfp + 6 * Np + 58 * 4 * Nfp + 30 * Np
+
+
+def bytes_per_elem_stage(N, word):
+    """Compulsory HBM bytes of one fused stage per element: read u and res, write u_out and
+    res (24 Np words), the geometric record (9 + 16 words) and four face records (16 B)."""
+    Np, _ = counts(N)
+    return 24 * Np * word + 25 * word + 16
+
+
+def cpu_baseline(N, n_sample):
+    """The FP64 oracle's LSRK4 step timed on the host on a smaller mesh of the same recipe."""
+    import numpy as np
+
+    import dginputs
+    from oracle import maxwell as W
+    from oracle import mesh as Mm
+    from oracle import refelem as R
+    v, e = dginputs.kuhn_cube(n_sample, jitter=0.15, permute=True)
+    m = Mm.Mesh(v, e, R.ref_element(N))
+    u = dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), *m.x)
+    dt = W.stable_dt(m)
+    t0 = time.perf_counter()
+    W.lsrk4_step(m, u, dt)
+    sec = time.perf_counter() - t0
+    flops = 5 * m.K * flops_per_elem_stage(N)
+    return {"value": flops / sec / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"one LSRK4 step (5 RHS) of the FP64 NumPy oracle on 6*{n_sample}^3 = {m.K} "
+                      f"tets, same jitter/permutation/field recipe, N={N}; {sec:.1f} s",
+            "seconds": sec}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--n", type=int, default=40)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU domain decomposition is a design, not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import dginputs
+    import paper_0901_1024_amd as P
+
+    N, n, prec = args.order, args.n, args.precision
+    Np, Nfp = counts(N)
+    word = 4 if prec == "f32" else 8
+    t_setup = time.perf_counter()
+    v, e = dginputs.kuhn_cube(n, jitter=0.15, permute=True)
+    s = P.Solver(v, e, N, prec, reorder=1, device=0)
+    x = s.nodes()
+    u0 = dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), x[0], x[1], x[2])
+    del x
+    s.set_fields(u0)
+    dt = s.stable_dt(0.5)
+    K = s.K
+    t_setup = time.perf_counter() - t_setup
+    print(f"setup done: K={K} N={N} {prec} dt={dt:.4e} ({t_setup:.1f} s)", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    e0 = s.energy()
+    s.solve(dt, args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    start.record(stream)
+    s.solve(dt, args.steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = start.elapsed_time(stop)
+    e1 = s.energy()
+    print(f"timed {args.steps} steps: {ms:.3f} ms (wall {wall * 1e3:.1f} ms); energy {e0:.6e} -> {e1:.6e}",
+          file=sys.stderr, flush=True)
+    if not (e1 <= e0 * (1 + 1e-5)):
+        print("energy grew: result invalid", file=sys.stderr)
+        sys.exit(1)
+
+    launches = 5 * args.steps
+    sec = ms / 1e3
+    per_launch_s = sec / launches
+    flops_launch = K * flops_per_elem_stage(N)
+    bytes_launch = K * bytes_per_elem_stage(N, word)
+    gflops = flops_launch * launches / sec / 1e9
+    gbs = bytes_launch / per_launch_s / 1e9
+    tflops_k = flops_launch / per_launch_s / 1e12
+    t_hbm = bytes_launch / (HBM_PEAK_GBS * 1e9)
+    t_cmp = flops_launch / (PEAKS_TFLOPS[prec] * 1e12)
+    if t_hbm >= t_cmp:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "mfma", "achieved": round(tflops_k, 2), "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
+                "frac": round(tflops_k / PEAKS_TFLOPS[prec], 4)}
+    roof["traffic"] = None
+    roof["kernel"] = f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>"
+    roof["hbm_gbs_algorithmic"] = round(gbs, 1)
+    roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    roof["tflops_algorithmic"] = round(tflops_k, 2)
+    roof["us_per_launch"] = round(per_launch_s * 1e6, 2)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"nodal DG Maxwell LSRK4, unit cube 6*{n}^3={K} jittered+permuted tets, "
+                               f"N={N}, {prec}, PEC walls, random smooth fields",
+                   "order": N, "K": K, "Np": Np, "stages_per_step": 5, "parallelism": "single GPU"},
+        "hbm_gbs": round(gbs, 1),
+        "dof_rhs_per_s": round(6 * Np * K * launches / sec, 1),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(N, args.cpu_sample_n)
+        cb["speedup_gpu_over_oracle"] = round(gflops / cb["value"], 1)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * dg.h — C ABI of libdg: nodal discontinuous Galerkin for Maxwell's equations on tetrahedra,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the semi-discrete DG operator of the paper's Sec. 2
+ * (eq. semidiscrete-dg: du/dt = -sum_nu D^nu F(u) + L[n.F - (n.F)*]) for Maxwell's equations
+ * in vacuum (Sec. 6, eq. maxwells-claws, eps = mu = 1) with the upwind flux of Sec. 6 and
+ * perfectly conducting walls (mirror state E+ = -E-, H+ = H-), and advances it with the
+ * five-stage fourth-order low-storage Runge-Kutta method named in Sec. 6.
+ *
+ * Conventions
+ *   Fields: six components in the order Ex, Ey, Ez, Hx, Hy, Hz.
+ *   Canonical field layout: [6][K][Np] contiguous, user element order, reference node order
+ *   (node lattice (i,j,k), i+j+k <= N, k outermost, then j, i innermost), after the
+ *   orientation fix below. Values are in the handle's working precision (double for DG_F64,
+ *   float for DG_F32).
+ *   Orientation fix: an element with det[v2-v1, v3-v1, v4-v1] < 0 has its local vertices 3
+ *   and 4 (1-based) swapped before anything else; node order refers to the fixed element.
+ *   Reference faces: F1 = (v1,v2,v3), F2 = (v1,v2,v4), F3 = (v2,v3,v4), F4 = (v1,v3,v4);
+ *   face nodes of each face in ascending node index.
+ *   Streams: every call that takes `stream` (a hipStream_t, NULL = the null stream) enqueues
+ *   its device work there and does not synchronise, unless stated otherwise.
+ *   Errors: every function returns 0 on success or a negative DG_E_* code; the text of the
+ *   last error of the calling thread is returned by dg_last_error(). No function aborts.
+ *   Thread safety: a handle must not be used by two threads at once.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DG_OK 0
+#define DG_E_ARG (-1)         /* invalid argument (NULL pointer, bad size, bad option) */
+#define DG_E_MESH (-2)        /* invalid mesh: degenerate element, face shared by > 2 elements */
+#define DG_E_UNSUPPORTED (-3) /* order outside 1..7, unknown precision, non-vacuum material */
+#define DG_E_OOM (-4)         /* device allocation failed or the workspace is too small */
+#define DG_E_HIP (-5)         /* a HIP runtime call failed; message in dg_last_error() */
+#define DG_E_STATE (-6)       /* handle has no device state (built with device = -1) */
+
+typedef struct dg_handle dg_handle;
+
+typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_precision;
+
+/* Mesh description. All arrays are host memory owned by the caller and only read during
+ * the call that receives them. */
+typedef struct {
+  int32_t nverts;         /* number of vertices */
+  const double* vxyz;     /* nverts x 3, row-major coordinates */
+  int32_t K;              /* number of tetrahedra, 1 <= K < 2^26 */
+  const int32_t* etov;    /* K x 4 vertex ids, 0-based, any orientation */
+  const int8_t* face_bc;  /* K x 4 or NULL: 0 = automatic (unmatched faces are perfectly
+                             conducting walls), 1 = wall; nonzero on a matched face is an
+                             error */
+  const double* eps;      /* must be NULL (vacuum) */
+  const double* mu;       /* must be NULL (vacuum) */
+} dg_mesh;
+
+typedef struct {
+  int32_t order;     /* polynomial order N, 1..7 */
+  int32_t precision; /* dg_precision */
+  int32_t reorder;   /* 0 = keep user element order internally, 1 = Morton locality order */
+  int32_t device;    /* HIP device ordinal, or -1 for a host-only handle (builder outputs
+                        only: dg_info, dg_nodes, dg_get_maps, dg_get_operators) */
+  int32_t reserved[4];
+} dg_opts;
+
+/* Sizes of a handle. */
+typedef struct {
+  int32_t order, Np, Nfp, K, precision, device;
+  int64_t state_words;     /* 6 * K * Np: length of one canonical field array */
+  size_t workspace_bytes;  /* device memory the handle uses */
+} dg_info_t;
+
+/* Device memory the handle needs for this mesh and options, in bytes (host-only work:
+ * builds nothing on the device). */
+int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_bytes);
+
+/* Build the reference operators (Sec. 2, eqs. dg-global-matrices, dg-reference-matrices,
+ * Fig. lifting-matrix), connectivity, geometric factors and face records in FP64 on the
+ * host, then upload them. `dev_workspace` is device memory of at least `workspace_bytes`
+ * (from dg_setup_query) owned by the caller and kept alive until dg_free, or NULL to let
+ * the library allocate. The uploads are enqueued on `stream`; the call returns after they
+ * complete. Fields start at zero. On failure *out is set to NULL. */
+int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace,
+             size_t workspace_bytes, void* stream, dg_handle** out);
+
+/* Release the handle (and the device memory the library allocated). NULL is accepted. */
+int dg_free(dg_handle* h);
+
+/* Text of the last error on this thread ("" if none). */
+const char* dg_last_error(void);
+
+int dg_info(const dg_handle* h, dg_info_t* info);
+
+/* Physical node coordinates, host array 3 x K x Np (x, then y, then z; canonical order). */
+int dg_nodes(const dg_handle* h, double* xyz);
+
+/* Canonical face-node maps, host arrays K x 4 x Nfp of flat node ids k*Np + n: vmapM is the
+ * node of face f of element k, vmapP the coinciding node of the neighbour across that face
+ * (itself on a wall). */
+int dg_get_maps(const dg_handle* h, int32_t* vmapM, int32_t* vmapP);
+
+/* Reference operators in FP64, host arrays: Dr, Ds, Dt (Np x Np row-major), LIFT
+ * (Np x 4Nfp row-major), mass M (Np x Np), nodes rst (Np x 3). Any pointer may be NULL. */
+int dg_get_operators(const dg_handle* h, double* Dr, double* Ds, double* Dt, double* LIFT,
+                     double* M, double* rst);
+
+/* Copy a canonical field array into the handle's state u (and zero the RK residual).
+ * `u` is host memory if on_device == 0 (the call then synchronises `stream`), else device
+ * memory. */
+int dg_set_fields(dg_handle* h, const void* u, int on_device, void* stream);
+
+/* Copy the handle's state u out as a canonical field array (host if on_device == 0, in
+ * which case the call synchronises `stream`). */
+int dg_get_fields(const dg_handle* h, void* u, int on_device, void* stream);
+
+/* Semi-discrete right-hand side (Sec. 2, eq. semidiscrete-dg; Maxwell flux of Sec. 6):
+ * rhs = curl/volume term + LIFT (Fscale * upwind flux), for the canonical device array
+ * `u_dev`, written to the canonical device array `rhs_dev` (both 6*K*Np values of the
+ * working precision, distinct buffers). Does not touch the handle's state. */
+int dg_rhs(dg_handle* h, const void* u_dev, void* rhs_dev, void* stream);
+
+/* One step of the five-stage low-storage RK4 method (Sec. 6) of size dt on the handle's
+ * state: for each stage i, res = a_i res + dt rhs(u); u = u + b_i res. */
+int dg_rk_step(dg_handle* h, double dt, void* stream);
+
+/* nsteps calls of dg_rk_step, launched from a captured HIP graph of two steps. */
+int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream);
+
+/* Discrete energy 1/2 sum_k J_k sum_fields u_k^T M u_k of the state, accumulated in double.
+ * Synchronises `stream`. */
+int dg_energy(const dg_handle* h, double* energy, void* stream);
+
+/* Time-step bound used by the tests and the benchmark: cfl * min over faces of 1/Fscale,
+ * divided by N^2 (host-only). */
+int dg_stable_dt(const dg_handle* h, double cfl, double* dt);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

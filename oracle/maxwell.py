@@ -51,15 +51,14 @@ def _dot(a, b):
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
 
 
-def volume_term(mesh: Mesh, u):
-    """(curl H, -curl E) at the nodes; u is (6, K, Np). Physical derivatives are
-    d/dx_nu = sum_mu (d r_mu/d x_nu) D_mu, constant per element."""
-    ref = mesh.ref
+def _curl_term(ref, G, u):
+    """(curl H, -curl E) at the nodes of u (6, k, Np) with inverse-map derivatives G (k,3,3).
+    Physical derivatives are d/dx_nu = sum_mu (d r_mu/d x_nu) D_mu, constant per element."""
     D = (ref.Dr, ref.Ds, ref.Dt)
-    # reference derivatives: (3 dirs, 6 fields, K, Np)
+    # reference derivatives: (3 dirs, 6 fields, k, Np)
     ref_d = np.stack([np.einsum("ij,fkj->fki", Dm, u) for Dm in D])
-    # physical derivatives: (3 dims nu, 6 fields, K, Np)
-    phys = np.einsum("kmn,mfki->nfki", mesh.G, ref_d)
+    # physical derivatives: (3 dims nu, 6 fields, k, Np)
+    phys = np.einsum("kmn,mfki->nfki", G, ref_d)
     dx, dy, dz = phys[0], phys[1], phys[2]
     Ex, Ey, Ez, Hx, Hy, Hz = range(6)
     curlH = np.stack([dy[Hz] - dz[Hy], dz[Hx] - dx[Hz], dx[Hy] - dy[Hx]])
@@ -67,48 +66,82 @@ def volume_term(mesh: Mesh, u):
     return np.concatenate([curlH, -curlE])
 
 
-def surface_flux(mesh: Mesh, u, alpha=1.0, eps=None, mu=None):
-    """[n.F - (n.F)*] at every face node, (6, K, 4, Nfp), not yet scaled by Fscale."""
-    K, Np = u.shape[1], u.shape[2]
-    flat = u.reshape(6, K * Np)
-    uM = flat[:, mesh.vmapM]
-    uP = flat[:, mesh.vmapP]
-    bnd = mesh.boundary[:, :, None]
+def volume_term(mesh: Mesh, u):
+    """(curl H, -curl E) at the nodes; u is (6, K, Np)."""
+    return _curl_term(mesh.ref, mesh.G, u)
+
+
+def _flux_terms(flat, vM, vP, bnd, nrm, alpha, imp):
+    """[n.F - (n.F)*] at face nodes given flat fields (6, K*Np), maps vM/vP (k,4,Nfp),
+    wall flags bnd (k,4), normals nrm (k,4,3) and impedances imp = (zm, zp, ym, yp)."""
+    uM = flat[:, vM]
+    uP = flat[:, vP]
+    b = bnd[:, :, None]
     # perfectly conducting wall: E+ = -E-, H+ = H-
-    uP = np.where(bnd[None], np.concatenate([-uM[:3], uM[3:]]), uP)
+    uP = np.where(b[None], np.concatenate([-uM[:3], uM[3:]]), uP)
     dE = uP[:3] - uM[:3]
     dH = uP[3:] - uM[3:]
-    n = np.moveaxis(mesh.n, 2, 0)[:, :, :, None]  # 3, K, 4, 1
-    if eps is None and mu is None:
-        zm = zp = ym = yp = np.ones((K, 4, 1))
-    else:
-        eps = np.ones(K) if eps is None else np.asarray(eps, dtype=np.float64)
-        mu = np.ones(K) if mu is None else np.asarray(mu, dtype=np.float64)
-        Z = np.sqrt(mu / eps)
-        nbr = mesh.EToE
-        zm = np.broadcast_to(Z[:, None, None], (K, 4, 1))
-        zp = Z[nbr][:, :, None]
-        ym, yp = 1.0 / zm, 1.0 / zp
+    n = np.moveaxis(nrm, 2, 0)[:, :, :, None]  # 3, k, 4, 1
+    zm, zp, ym, yp = imp
     fE = _cross(n, zp * dH - alpha * _cross(n, dE)) / (zm + zp)
     fH = _cross(n, -yp * dE - alpha * _cross(n, dH)) / (ym + yp)
     return np.concatenate([fE, fH])
 
 
+def _impedances(mesh, elems, eps, mu):
+    k = elems.size
+    if eps is None and mu is None:
+        one = np.ones((k, 4, 1))
+        return one, one, one, one
+    eps = np.ones(mesh.K) if eps is None else np.asarray(eps, dtype=np.float64)
+    mu = np.ones(mesh.K) if mu is None else np.asarray(mu, dtype=np.float64)
+    Z = np.sqrt(mu / eps)
+    zm = np.broadcast_to(Z[elems][:, None, None], (k, 4, 1))
+    zp = Z[mesh.EToE[elems]][:, :, None]
+    return zm, zp, 1.0 / zm, 1.0 / zp
+
+
+def surface_flux(mesh: Mesh, u, alpha=1.0, eps=None, mu=None):
+    """[n.F - (n.F)*] at every face node, (6, K, 4, Nfp), not yet scaled by Fscale."""
+    K, Np = u.shape[1], u.shape[2]
+    elems = np.arange(K)
+    return _flux_terms(u.reshape(6, K * Np), mesh.vmapM, mesh.vmapP, mesh.boundary, mesh.n, alpha,
+                       _impedances(mesh, elems, eps, mu))
+
+
+def _assemble(ref, vol, flux, Fscale, eps_k, mu_k):
+    k, Nfp = vol.shape[1], ref.Nfp
+    scaled = (flux * Fscale[None, :, :, None]).reshape(6, k, 4 * Nfp)
+    out = vol + np.einsum("ij,fkj->fki", ref.LIFT, scaled)
+    if eps_k is not None:
+        out[:3] /= eps_k[None, :, None]
+    if mu_k is not None:
+        out[3:] /= mu_k[None, :, None]
+    return out
+
+
 def rhs(mesh: Mesh, u, alpha=1.0, eps=None, mu=None):
     """Semi-discrete right-hand side du/dt, u of shape (6, K, Np), FP64."""
-    ref = mesh.ref
-    K, Np, Nfp = u.shape[1], ref.Np, ref.Nfp
     vol = volume_term(mesh, u)
     flux = surface_flux(mesh, u, alpha, eps, mu)                    # 6, K, 4, Nfp
-    scaled = (flux * mesh.Fscale[None, :, :, None]).reshape(6, K, 4 * Nfp)
-    lift = np.einsum("ij,fkj->fki", ref.LIFT, scaled)
-    out = vol + lift
-    if eps is not None or mu is not None:
-        e = np.ones(K) if eps is None else np.asarray(eps, dtype=np.float64)
-        m = np.ones(K) if mu is None else np.asarray(mu, dtype=np.float64)
-        out[:3] /= e[None, :, None]
-        out[3:] /= m[None, :, None]
-    return out
+    e = None if eps is None else np.asarray(eps, dtype=np.float64)
+    m = None if mu is None else np.asarray(mu, dtype=np.float64)
+    return _assemble(mesh.ref, vol, flux, mesh.Fscale, e, m)
+
+
+def rhs_at(mesh: Mesh, u, elems, alpha=1.0):
+    """The same right-hand side (vacuum) evaluated only at the elements `elems`: (6, len, Np).
+    Face maps are computed for those elements only, so the mesh may be built with
+    compute_maps=False."""
+    from .mesh import face_maps
+    elems = np.asarray(elems, dtype=np.int64)
+    ref = mesh.ref
+    K, Np = u.shape[1], u.shape[2]
+    vol = _curl_term(ref, mesh.G[elems], u[:, elems, :])
+    vM, vP = face_maps(mesh.x, mesh.EToE, mesh.EToF, ref.Fmask, elems)
+    flux = _flux_terms(u.reshape(6, K * Np), vM, vP, mesh.boundary[elems], mesh.n[elems], alpha,
+                       _impedances(mesh, elems, None, None))
+    return _assemble(ref, vol, flux, mesh.Fscale[elems], None, None)
 
 
 def lsrk4_step(mesh: Mesh, u, dt, res=None, **kw):
@@ -119,6 +152,34 @@ def lsrk4_step(mesh: Mesh, u, dt, res=None, **kw):
         res = a * res + dt * rhs(mesh, u, **kw)
         u = u + b * res
     return u, res
+
+
+def face_rings(mesh: Mesh, elems, depth):
+    """Sets S_0 = elems, S_d = S_{d-1} plus its face neighbours, for d = 0..depth."""
+    rings = [np.unique(np.asarray(elems, dtype=np.int64))]
+    for _ in range(depth):
+        prev = rings[-1]
+        rings.append(np.unique(np.concatenate([prev, mesh.EToE[prev].ravel()])))
+    return rings
+
+
+def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0):
+    """One LSRK4 step from res = 0, evaluated only where it is needed for `elems`.
+
+    A stage's right-hand side at an element reads only that element and its face neighbours,
+    so after five stages the result at `elems` depends on the elements within five face
+    steps. Stage i (1..5) evaluates the right-hand side and updates res and u on the ring of
+    depth 5 - i; everything read there was updated at the previous stage. Returns u at
+    `elems` (6, len, Np), identical to lsrk4_step(...)[0][:, elems]."""
+    rings = face_rings(mesh, elems, 5)
+    u = np.array(u, dtype=np.float64, copy=True)
+    res = np.zeros_like(u)
+    for i, (a, b) in enumerate(zip(RK4A, RK4B)):
+        S = rings[4 - i]
+        r = rhs_at(mesh, u, S, alpha)
+        res[:, S] = a * res[:, S] + dt * r
+        u[:, S] = u[:, S] + b * res[:, S]
+    return u[:, np.asarray(elems, dtype=np.int64)]
 
 
 def energy(mesh: Mesh, u, eps=None, mu=None):

@@ -1,0 +1,259 @@
+"""Python binding of libdg (include/dg.h): nodal DG Maxwell on tetrahedra on one MI355X.
+
+Argument marshalling only: every step of the operator runs in the library's HIP kernels.
+PyTorch supplies device memory (the workspace and field buffers) and the HIP stream. The
+library must have been built (`python -m paper_0901_1024_amd.build`); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdg.so")
+
+DG_F64 = 0
+DG_F32 = 1
+_PREC = {"f64": DG_F64, "f32": DG_F32}
+_ERRS = {-1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_UNSUPPORTED", -4: "DG_E_OOM", -5: "DG_E_HIP",
+         -6: "DG_E_STATE"}
+
+# every symbol declared in include/dg.h
+EXPORTS = ["dg_setup_query", "dg_setup", "dg_free", "dg_last_error", "dg_info", "dg_nodes",
+           "dg_get_maps", "dg_get_operators", "dg_set_fields", "dg_get_fields", "dg_rhs",
+           "dg_rk_step", "dg_solve", "dg_energy", "dg_stable_dt"]
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nverts", ctypes.c_int32), ("vxyz", ctypes.POINTER(ctypes.c_double)),
+                ("K", ctypes.c_int32), ("etov", ctypes.POINTER(ctypes.c_int32)),
+                ("face_bc", ctypes.POINTER(ctypes.c_int8)), ("eps", ctypes.POINTER(ctypes.c_double)),
+                ("mu", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("reorder", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("Np", ctypes.c_int32), ("Nfp", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("state_words", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # PyTorch ships its own HIP runtime (same SONAME as /opt/rocm's, requested under another
+        # name). Loading torch first makes libdg bind to that one runtime instead of bringing a
+        # second HIP/HSA runtime into the process, which would not see the device.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0901_1024_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.dg_last_error.restype = ctypes.c_char_p
+        L.dg_setup_query.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_size_t)]
+        L.dg_setup.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts), vp, ctypes.c_size_t, vp,
+                               ctypes.POINTER(vp)]
+        L.dg_free.argtypes = [vp]
+        L.dg_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.dg_nodes.argtypes = [vp, vp]
+        L.dg_get_maps.argtypes = [vp, vp, vp]
+        L.dg_get_operators.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.dg_set_fields.argtypes = [vp, vp, i32, vp]
+        L.dg_get_fields.argtypes = [vp, vp, i32, vp]
+        L.dg_rhs.argtypes = [vp, vp, vp, vp]
+        L.dg_rk_step.argtypes = [vp, dbl, vp]
+        L.dg_solve.argtypes = [vp, dbl, i64, vp]
+        L.dg_energy.argtypes = [vp, ctypes.POINTER(dbl), vp]
+        L.dg_stable_dt.argtypes = [vp, dbl, ctypes.POINTER(dbl)]
+        for name in EXPORTS:
+            if name != "dg_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise DGError(rc, lib().dg_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _mesh_struct(vxyz, etov, face_bc=None):
+    vxyz = np.ascontiguousarray(vxyz, dtype=np.float64)
+    etov = np.ascontiguousarray(etov, dtype=np.int32)
+    m = _Mesh()
+    m.nverts = vxyz.shape[0]
+    m.vxyz = _ptr(vxyz, ctypes.c_double)
+    m.K = etov.shape[0]
+    m.etov = _ptr(etov, ctypes.c_int32)
+    keep = [vxyz, etov]
+    if face_bc is not None:
+        fb = np.ascontiguousarray(face_bc, dtype=np.int8)
+        m.face_bc = _ptr(fb, ctypes.c_int8)
+        keep.append(fb)
+    return m, keep
+
+
+def _opts_struct(order, precision, reorder, device):
+    o = _Opts()
+    o.order = order
+    o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    o.reorder = reorder
+    o.device = device
+    return o
+
+
+def setup_query(vxyz, etov, order, precision="f64", reorder=1):
+    m, _keep = _mesh_struct(vxyz, etov)
+    o = _opts_struct(order, precision, reorder, 0)
+    n = ctypes.c_size_t()
+    _check(lib().dg_setup_query(ctypes.byref(m), ctypes.byref(o), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One mesh, one order, one precision: a handle of libdg.
+
+    device >= 0: the workspace is a torch uint8 tensor on cuda:device (PyTorch owns the HBM);
+    device = -1: host-only handle (builder outputs only).
+    """
+
+    def __init__(self, vxyz, etov, order, precision="f64", reorder=1, device=0, face_bc=None,
+                 stream=None):
+        L = lib()
+        self.order = order
+        self.precision = precision
+        self.device = device
+        m, keep = _mesh_struct(vxyz, etov, face_bc)
+        o = _opts_struct(order, precision, reorder, device)
+        h = ctypes.c_void_p()
+        self._ws = None
+        if device >= 0:
+            import torch
+            n = ctypes.c_size_t()
+            _check(L.dg_setup_query(ctypes.byref(m), ctypes.byref(o), ctypes.byref(n)))
+            with torch.cuda.device(device):
+                self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=f"cuda:{device}")
+                base = self._ws.data_ptr()
+                aligned = (base + 255) & ~255
+                _check(L.dg_setup(ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(aligned),
+                                  ctypes.c_size_t(n.value), _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            _check(L.dg_setup(ctypes.byref(m), ctypes.byref(o), None, 0, None, ctypes.byref(h)))
+        del keep
+        self._h = h
+        info = _Info()
+        _check(L.dg_info(h, ctypes.byref(info)))
+        self.Np, self.Nfp, self.K = info.Np, info.Nfp, info.K
+        self.workspace_bytes = info.workspace_bytes
+        self.dtype = np.float64 if o.precision == DG_F64 else np.float32
+
+    # -- lifecycle -------------------------------------------------------------------------
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dg_free(self._h)
+            self._h = ctypes.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- host outputs ----------------------------------------------------------------------
+    def nodes(self):
+        out = np.empty((3, self.K, self.Np), dtype=np.float64)
+        _check(lib().dg_nodes(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def get_maps(self):
+        vM = np.empty((self.K, 4, self.Nfp), dtype=np.int32)
+        vP = np.empty_like(vM)
+        _check(lib().dg_get_maps(self._h, vM.ctypes.data_as(ctypes.c_void_p), vP.ctypes.data_as(ctypes.c_void_p)))
+        return vM, vP
+
+    def get_operators(self):
+        Np, Nfp = self.Np, self.Nfp
+        Dr, Ds, Dt, M = (np.empty((Np, Np)) for _ in range(4))
+        LIFT = np.empty((Np, 4 * Nfp))
+        rst = np.empty((Np, 3))
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib().dg_get_operators(self._h, vp(Dr), vp(Ds), vp(Dt), vp(LIFT), vp(M), vp(rst)))
+        return {"Dr": Dr, "Ds": Ds, "Dt": Dt, "LIFT": LIFT, "M": M, "rst": rst}
+
+    def stable_dt(self, cfl=0.5):
+        d = ctypes.c_double()
+        _check(lib().dg_stable_dt(self._h, cfl, ctypes.byref(d)))
+        return d.value
+
+    # -- device state ----------------------------------------------------------------------
+    def set_fields(self, u, stream=None):
+        """u: canonical (6, K, Np) array, numpy (host) or torch CUDA tensor of the working dtype."""
+        if isinstance(u, np.ndarray):
+            a = np.ascontiguousarray(u, dtype=self.dtype)
+            assert a.size == 6 * self.K * self.Np
+            _check(lib().dg_set_fields(self._h, a.ctypes.data_as(ctypes.c_void_p), 0, _stream_ptr(stream)))
+        else:
+            self._check_tensor(u)
+            _check(lib().dg_set_fields(self._h, ctypes.c_void_p(u.data_ptr()), 1, _stream_ptr(stream)))
+
+    def get_fields(self, out=None, stream=None):
+        """Canonical (6, K, Np) fields: into `out` (torch CUDA tensor) or a new numpy array."""
+        if out is None:
+            a = np.empty((6, self.K, self.Np), dtype=self.dtype)
+            _check(lib().dg_get_fields(self._h, a.ctypes.data_as(ctypes.c_void_p), 0, _stream_ptr(stream)))
+            return a
+        self._check_tensor(out)
+        _check(lib().dg_get_fields(self._h, ctypes.c_void_p(out.data_ptr()), 1, _stream_ptr(stream)))
+        return out
+
+    def rhs(self, u, out, stream=None):
+        """Right-hand side of canonical device tensor u into canonical device tensor out."""
+        self._check_tensor(u)
+        self._check_tensor(out)
+        _check(lib().dg_rhs(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                            _stream_ptr(stream)))
+        return out
+
+    def rk_step(self, dt, stream=None):
+        _check(lib().dg_rk_step(self._h, float(dt), _stream_ptr(stream)))
+
+    def solve(self, dt, nsteps, stream=None):
+        _check(lib().dg_solve(self._h, float(dt), int(nsteps), _stream_ptr(stream)))
+
+    def energy(self, stream=None):
+        e = ctypes.c_double()
+        _check(lib().dg_energy(self._h, ctypes.byref(e), _stream_ptr(stream)))
+        return e.value
+
+    def _check_tensor(self, t):
+        import torch
+        want = torch.float64 if self.dtype == np.float64 else torch.float32
+        if not (t.is_cuda and t.dtype == want and t.is_contiguous() and t.numel() == 6 * self.K * self.Np):
+            raise DGError(-1, "expected a contiguous CUDA tensor of 6*K*Np values of the working dtype")

@@ -1,0 +1,461 @@
+// C ABI of libdg (see include/dg.h): handle lifetime, host build, uploads, and the stage
+// sequence of the five-stage low-storage RK4 method of Sec. 6.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+#include "host/meshbuild.hpp"
+#include "host/refops.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients.
+constexpr double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                            -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+constexpr double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                            1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                            2277821191437.0 / 14882151754819.0};
+
+struct Layout {
+  size_t state = 0;  // bytes of one [K][6][Np] array
+  size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
+      off_elem_of, off_pos_of, off_partial, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(int K, int Np, int Nfp, size_t ts) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.state = size_t(K) * 6 * Np * ts;
+  L.off_u0 = take(L.state);
+  L.off_u1 = take(L.state);
+  L.off_res = take(L.state);
+  L.off_tmp = take(L.state);
+  L.off_geo = take(size_t(K) * dgh::kGeoStride * ts);
+  L.off_fcode = take(size_t(K) * 4 * sizeof(int32_t));
+  L.off_ops = take((size_t(4) * Np * Np + size_t(Np) * 4 * Nfp) * ts);
+  L.off_fmask = take(size_t(4) * Nfp * sizeof(int32_t));
+  L.off_nbr = take(size_t(96) * Nfp * sizeof(int32_t));
+  L.off_elem_of = take(size_t(K) * sizeof(int32_t));
+  L.off_pos_of = take(size_t(K) * sizeof(int32_t));
+  L.off_partial = take(size_t((K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems) * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
+  if (!mesh || !opts) return fail(DG_E_ARG, "mesh and opts must not be NULL");
+  if (!mesh->vxyz || !mesh->etov) return fail(DG_E_ARG, "vxyz and etov must not be NULL");
+  if (mesh->K <= 0 || mesh->nverts < 4) return fail(DG_E_ARG, "empty mesh");
+  if (opts->order < 1 || opts->order > 7) return fail(DG_E_UNSUPPORTED, "order must be in 1..7");
+  if (opts->precision != DG_F64 && opts->precision != DG_F32)
+    return fail(DG_E_UNSUPPORTED, "unknown precision");
+  if (mesh->eps || mesh->mu) return fail(DG_E_UNSUPPORTED, "only vacuum (eps = mu = NULL) is supported");
+  if (opts->reorder < 0 || opts->reorder > 1) return fail(DG_E_ARG, "reorder must be 0 or 1");
+  return DG_OK;
+}
+
+}  // namespace
+
+struct dg_handle {
+  dgh::RefOps ref;
+  dgh::MeshData mesh;
+  int N = 0, Np = 0, Nfp = 0, K = 0, prec = 0, device = -1;
+  size_t ts = 8;
+  Layout lay;
+  char* ws = nullptr;
+  bool own_ws = false;
+  int cur = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  double graph_dt = 0.0;
+  int graph_cur = -1;
+
+  bool f64() const { return prec == DG_F64; }
+  void* at(size_t off) const { return ws + off; }
+  void* u(int i) const { return at(i == 0 ? lay.off_u0 : lay.off_u1); }
+  dgk::OpsView ops() const {
+    const size_t nn = size_t(Np) * Np * ts;
+    dgk::OpsView o;
+    o.Dr = at(lay.off_ops);
+    o.Ds = at(lay.off_ops + nn);
+    o.Dt = at(lay.off_ops + 2 * nn);
+    o.M = at(lay.off_ops + 3 * nn);
+    o.LIFT = at(lay.off_ops + 4 * nn);
+    o.fmask = static_cast<const int32_t*>(at(lay.off_fmask));
+    o.nbrnode = static_cast<const int32_t*>(at(lay.off_nbr));
+    return o;
+  }
+  void drop_graph() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_cur = -1;
+  }
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                 \
+  do {                                                \
+    hipError_t _e = (call);                           \
+    if (_e != hipSuccess) return hip_fail(_e, #call); \
+  } while (0)
+
+template <typename T>
+std::vector<char> convert(const std::vector<double>& v) {
+  std::vector<char> out(v.size() * sizeof(T));
+  T* p = reinterpret_cast<T*>(out.data());
+  for (size_t i = 0; i < v.size(); ++i) p[i] = static_cast<T>(v[i]);
+  return out;
+}
+
+std::vector<char> to_prec(const std::vector<double>& v, bool f64) {
+  return f64 ? convert<double>(v) : convert<float>(v);
+}
+
+int upload(dg_handle* h, hipStream_t s) {
+  const auto& R = h->ref;
+  const auto& M = h->mesh;
+  const int K = h->K;
+  // geometric records in internal order
+  std::vector<double> geo(size_t(K) * dgh::kGeoStride);
+  for (int i = 0; i < K; ++i)
+    std::memcpy(&geo[size_t(i) * dgh::kGeoStride], &M.geo[size_t(M.elem_of[i]) * dgh::kGeoStride],
+                sizeof(double) * dgh::kGeoStride);
+  std::vector<double> ops;
+  ops.reserve(size_t(4) * h->Np * h->Np + size_t(h->Np) * 4 * h->Nfp);
+  for (const auto* m : {&R.Dr, &R.Ds, &R.Dt, &R.M}) ops.insert(ops.end(), m->begin(), m->end());
+  ops.insert(ops.end(), R.LIFT.begin(), R.LIFT.end());
+  std::vector<char> geo_b = to_prec(geo, h->f64()), ops_b = to_prec(ops, h->f64());
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_geo), geo_b.data(), geo_b.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_ops), ops_b.data(), ops_b.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_fcode), M.face_code.data(), M.face_code.size() * 4,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_fmask), R.Fmask.data(), R.Fmask.size() * 4, hipMemcpyHostToDevice, s));
+  std::vector<int32_t> nbr(R.nbr_node.begin(), R.nbr_node.end());
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_nbr), nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_elem_of), M.elem_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_pos_of), M.pos_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(h->u(0), 0, h->lay.state, s));
+  HIP_TRY(hipMemsetAsync(h->u(1), 0, h->lay.state, s));
+  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.state, s));
+  HIP_TRY(hipStreamSynchronize(s));  // host staging buffers die at return
+  return DG_OK;
+}
+
+int need_device(const dg_handle* h) {
+  if (!h) return fail(DG_E_ARG, "NULL handle");
+  if (h->device < 0) return fail(DG_E_STATE, "handle was built host-only (device = -1)");
+  return DG_OK;
+}
+
+int set_device(const dg_handle* h) {
+  HIP_TRY(hipSetDevice(h->device));
+  return DG_OK;
+}
+
+int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, double b, double dt,
+                 hipStream_t s) {
+  dgk::StageArgs args;
+  args.u_in = in;
+  args.out = out;
+  args.res = h->at(h->lay.off_res);
+  args.geo = h->at(h->lay.off_geo);
+  args.fcode = static_cast<const int32_t*>(h->at(h->lay.off_fcode));
+  args.K = h->K;
+  args.a = a;
+  args.b = b;
+  args.dt = dt;
+  HIP_TRY(dgk::launch_stage(h->N, h->f64(), stage, h->ops(), args, s));
+  return DG_OK;
+}
+
+int rk_step_launch(dg_handle* h, double dt, hipStream_t s) {
+  for (int i = 0; i < 5; ++i) {
+    int rc = stage_launch(h, true, h->u(h->cur), h->u(1 - h->cur), kRkA[i], kRkB[i], dt, s);
+    if (rc) return rc;
+    h->cur ^= 1;
+  }
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_bytes) {
+  int rc = check_inputs(mesh, opts);
+  if (rc) return rc;
+  if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
+  const int N = opts->order;
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  *workspace_bytes = make_layout(mesh->K, Np, Nfp, opts->precision == DG_F64 ? 8 : 4).total;
+  return DG_OK;
+}
+
+int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size_t workspace_bytes,
+             void* stream, dg_handle** out) {
+  if (out) *out = nullptr;
+  if (!out) return fail(DG_E_ARG, "out must not be NULL");
+  int rc = check_inputs(mesh, opts);
+  if (rc) return rc;
+  std::unique_ptr<dg_handle> h(new (std::nothrow) dg_handle);
+  if (!h) return fail(DG_E_OOM, "host allocation failed");
+  try {
+    h->ref = dgh::build_ref_ops(opts->order);
+    h->mesh = dgh::build_mesh(h->ref, mesh->nverts, mesh->vxyz, mesh->K, mesh->etov, mesh->face_bc,
+                              opts->reorder);
+  } catch (const std::bad_alloc&) {
+    return fail(DG_E_OOM, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(DG_E_MESH, ex.what());
+  }
+  h->N = opts->order;
+  h->Np = h->ref.Np;
+  h->Nfp = h->ref.Nfp;
+  h->K = mesh->K;
+  h->prec = opts->precision;
+  h->ts = h->f64() ? 8 : 4;
+  h->device = opts->device;
+  h->lay = make_layout(h->K, h->Np, h->Nfp, h->ts);
+  if (h->device >= 0) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = set_device(h.get());
+    if (rc) return rc;
+    if (dev_workspace) {
+      if (workspace_bytes < h->lay.total) return fail(DG_E_OOM, "workspace smaller than dg_setup_query");
+      if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0)
+        return fail(DG_E_ARG, "workspace must be 256-byte aligned");
+      h->ws = static_cast<char*>(dev_workspace);
+    } else {
+      void* p = nullptr;
+      hipError_t e = hipMalloc(&p, h->lay.total);
+      if (e != hipSuccess) return fail(DG_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      h->ws = static_cast<char*>(p);
+      h->own_ws = true;
+    }
+    rc = upload(h.get(), s);
+    if (rc) {
+      if (h->own_ws) hipFree(h->ws);
+      return rc;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      if (h->own_ws) hipFree(h->ws);
+      return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+  }
+  *out = h.release();
+  return DG_OK;
+}
+
+int dg_free(dg_handle* h) {
+  if (!h) return DG_OK;
+  if (h->device >= 0) {
+    hipSetDevice(h->device);
+    h->drop_graph();
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->own_ws && h->ws) hipFree(h->ws);
+  }
+  delete h;
+  return DG_OK;
+}
+
+int dg_info(const dg_handle* h, dg_info_t* info) {
+  if (!h || !info) return fail(DG_E_ARG, "NULL argument");
+  info->order = h->N;
+  info->Np = h->Np;
+  info->Nfp = h->Nfp;
+  info->K = h->K;
+  info->precision = h->prec;
+  info->device = h->device;
+  info->state_words = int64_t(6) * h->K * h->Np;
+  info->workspace_bytes = h->lay.total;
+  return DG_OK;
+}
+
+int dg_nodes(const dg_handle* h, double* xyz) {
+  if (!h || !xyz) return fail(DG_E_ARG, "NULL argument");
+  std::memcpy(xyz, h->mesh.x.data(), h->mesh.x.size() * sizeof(double));
+  return DG_OK;
+}
+
+int dg_get_maps(const dg_handle* h, int32_t* vmapM, int32_t* vmapP) {
+  if (!h || !vmapM || !vmapP) return fail(DG_E_ARG, "NULL argument");
+  dgh::canonical_maps(h->ref, h->mesh, vmapM, vmapP);
+  return DG_OK;
+}
+
+int dg_get_operators(const dg_handle* h, double* Dr, double* Ds, double* Dt, double* LIFT, double* M,
+                     double* rst) {
+  if (!h) return fail(DG_E_ARG, "NULL handle");
+  const auto& R = h->ref;
+  if (Dr) std::copy(R.Dr.begin(), R.Dr.end(), Dr);
+  if (Ds) std::copy(R.Ds.begin(), R.Ds.end(), Ds);
+  if (Dt) std::copy(R.Dt.begin(), R.Dt.end(), Dt);
+  if (LIFT) std::copy(R.LIFT.begin(), R.LIFT.end(), LIFT);
+  if (M) std::copy(R.M.begin(), R.M.end(), M);
+  if (rst)
+    for (int n = 0; n < R.Np; ++n) rst[3 * n] = R.r[n], rst[3 * n + 1] = R.s[n], rst[3 * n + 2] = R.t[n];
+  return DG_OK;
+}
+
+int dg_set_fields(dg_handle* h, const void* u, int on_device, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!u) return fail(DG_E_ARG, "NULL field array");
+  rc = set_device(h);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* src = u;
+  if (!on_device) {
+    HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_tmp), u, h->lay.state, hipMemcpyHostToDevice, s));
+    src = h->at(h->lay.off_tmp);
+  }
+  HIP_TRY(dgk::launch_to_internal(h->f64(), src, h->u(h->cur),
+                                  static_cast<const int32_t*>(h->at(h->lay.off_elem_of)), h->K, h->Np, s));
+  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.state, s));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(s));
+  return DG_OK;
+}
+
+int dg_get_fields(const dg_handle* h, void* u, int on_device, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!u) return fail(DG_E_ARG, "NULL field array");
+  rc = set_device(h);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* dst = on_device ? u : h->at(h->lay.off_tmp);
+  HIP_TRY(dgk::launch_to_canonical(h->f64(), h->u(h->cur), dst,
+                                   static_cast<const int32_t*>(h->at(h->lay.off_pos_of)), h->K, h->Np, s));
+  if (!on_device) {
+    HIP_TRY(hipMemcpyAsync(u, dst, h->lay.state, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return DG_OK;
+}
+
+int dg_rhs(dg_handle* h, const void* u_dev, void* rhs_dev, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(DG_E_ARG, "u and rhs must be distinct device arrays");
+  rc = set_device(h);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* in = h->u(1 - h->cur);  // the spare state buffer is free between steps
+  void* out = h->at(h->lay.off_tmp);
+  HIP_TRY(dgk::launch_to_internal(h->f64(), u_dev, in, static_cast<const int32_t*>(h->at(h->lay.off_elem_of)),
+                                  h->K, h->Np, s));
+  rc = stage_launch(h, false, in, out, 0, 0, 0, s);
+  if (rc) return rc;
+  HIP_TRY(dgk::launch_to_canonical(h->f64(), out, rhs_dev, static_cast<const int32_t*>(h->at(h->lay.off_pos_of)),
+                                   h->K, h->Np, s));
+  return DG_OK;
+}
+
+int dg_rk_step(dg_handle* h, double dt, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!std::isfinite(dt)) return fail(DG_E_ARG, "dt must be finite");
+  rc = set_device(h);
+  if (rc) return rc;
+  return rk_step_launch(h, dt, static_cast<hipStream_t>(stream));
+}
+
+int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!std::isfinite(dt) || nsteps < 0) return fail(DG_E_ARG, "bad dt or nsteps");
+  rc = set_device(h);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (nsteps >= 2) {
+    // Two steps (ten stages) return the ping-pong state buffers to their starting roles, so
+    // one captured graph replays any even number of steps.
+    if (!h->gexec || h->graph_dt != dt || h->graph_cur != h->cur) {
+      h->drop_graph();
+      const int saved = h->cur;
+      HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      int r1 = rk_step_launch(h, dt, h->cap_stream);
+      int r2 = r1 ? r1 : rk_step_launch(h, dt, h->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+      h->cur = saved;
+      if (r2) {
+        if (g) hipGraphDestroy(g);
+        return r2;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      h->graph = g;
+      HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+      h->graph_dt = dt;
+      h->graph_cur = h->cur;
+    }
+    for (int64_t i = 0; i + 1 < nsteps; i += 2) HIP_TRY(hipGraphLaunch(h->gexec, s));
+  }
+  if (nsteps % 2) return rk_step_launch(h, dt, s);
+  return DG_OK;
+}
+
+int dg_energy(const dg_handle* h, double* energy, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!energy) return fail(DG_E_ARG, "NULL energy");
+  rc = set_device(h);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = (h->K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems;
+  double* partial = static_cast<double*>(h->at(h->lay.off_partial));
+  HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo), h->K, partial, s));
+  std::vector<double> host(nb);
+  HIP_TRY(hipMemcpyAsync(host.data(), partial, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double e = 0.0;
+  for (double v : host) e += v;
+  *energy = e;
+  return DG_OK;
+}
+
+int dg_stable_dt(const dg_handle* h, double cfl, double* dt) {
+  if (!h || !dt) return fail(DG_E_ARG, "NULL argument");
+  double mn = 1e300;
+  for (int k = 0; k < h->K; ++k)
+    for (int f = 0; f < 4; ++f)
+      mn = std::min(mn, 1.0 / h->mesh.geo[size_t(k) * dgh::kGeoStride + dgh::kGeoNormal + 4 * f + 3]);
+  *dt = cfl * mn / (double(h->N) * h->N);
+  return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Launch interface of the device kernels (used by the C ABI layer).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace dgk {
+
+// Device views of the per-handle constant data.
+struct OpsView {
+  const void* Dr;
+  const void* Ds;
+  const void* Dt;
+  const void* LIFT;
+  const void* M;
+  const int32_t* fmask;    // 4 x Nfp
+  const int32_t* nbrnode;  // 4 x 4 x 6 x Nfp
+};
+
+struct StageArgs {
+  const void* u_in;  // internal layout [K][6][Np]
+  void* out;         // rhs (RHS mode) or u_out (stage mode), internal layout
+  void* res;         // RK residual, internal layout (stage mode only)
+  const void* geo;   // [K][26]
+  const int32_t* fcode;  // [K][4]
+  int K;
+  double a, b, dt;   // stage coefficients (stage mode only)
+};
+
+// Elements per workgroup tile of the stage kernel for order N.
+int tile_elems(int N);
+
+// One RHS evaluation (stage == false) or one fused LSRK4 stage (stage == true).
+hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
+                        hipStream_t s);
+
+// Canonical [6][K][Np] <-> internal [K][6][Np] (internal position i holds user element
+// elem_of[i]).
+hipError_t launch_to_internal(bool f64, const void* canon, void* internal, const int32_t* elem_of,
+                              int K, int Np, hipStream_t s);
+hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, const int32_t* pos_of,
+                               int K, int Np, hipStream_t s);
+
+// Partial energies: one double per block of `energy_block_elems` elements written to
+// `partial`; the caller sums them.
+constexpr int kEnergyBlockElems = 64;
+hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, int K,
+                         double* partial, hipStream_t s);
+
+}  // namespace dgk

@@ -1,0 +1,98 @@
+"""Host builder of libdg (C++, FP64) against the oracle, and the C ABI surface (CPU only).
+
+The builder and the oracle are separate codes: nodes by tangent-frame warps vs per-edge
+warps, classical vs orthonormal Jacobi recurrences, Newton vs eigenvalue GLL points, own LU
+vs LAPACK, combinatorial vs nearest-coordinate face maps.
+"""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import dginputs
+import paper_0901_1024_amd as P
+from conftest import ROOT
+from oracle import mesh as Mm
+from oracle import refelem as R
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(f"{ROOT}/include/dg.h").read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(dg_\w+)\s*\(", header, re.M))
+    assert declared == set(P.EXPORTS)
+    L = ctypes.CDLL(P.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("N", range(1, 8))
+def test_builder_operators_match_oracle(N):
+    v, e = dginputs.kuhn_cube(1)
+    s = P.Solver(v, e, N, device=-1)
+    ops = s.get_operators()
+    ref = R.ref_element(N)
+    assert np.max(np.abs(ops["rst"] - ref.rst)) <= 1e-14
+    for name in ("Dr", "Ds", "Dt"):
+        assert np.max(np.abs(ops[name] - getattr(ref, name))) <= 1e-12 * max(1.0, np.max(np.abs(getattr(ref, name))))
+    assert np.max(np.abs(ops["LIFT"] - ref.LIFT)) <= 1e-13 * np.max(np.abs(ref.LIFT))
+    assert np.max(np.abs(ops["M"] - ref.M)) <= 1e-14
+
+
+@pytest.mark.parametrize("N,n,jitter,permute", [(1, 2, 0.15, True), (3, 3, 0.15, True), (4, 2, 0.0, False),
+                                                (7, 1, 0.15, True)])
+def test_builder_maps_are_bit_identical_to_oracle(N, n, jitter, permute):
+    v, e = dginputs.kuhn_cube(n, jitter=jitter, permute=permute)
+    s = P.Solver(v, e, N, device=-1)
+    m = Mm.Mesh(v, e, R.ref_element(N))
+    vM, vP = s.get_maps()
+    assert np.array_equal(vM, m.vmapM)
+    assert np.array_equal(vP, m.vmapP)
+    assert np.max(np.abs(s.nodes() - m.x)) <= 1e-14
+    dt_o = 0.5 * np.min(1.0 / m.Fscale) / N ** 2
+    assert abs(s.stable_dt(0.5) - dt_o) <= 1e-14 * dt_o
+
+
+def test_builder_orients_negative_elements_like_the_oracle():
+    v, e = dginputs.kuhn_cube(2, jitter=0.1)
+    e = e.copy()
+    e[::3, [2, 3]] = e[::3, [3, 2]]
+    s = P.Solver(v, e, 3, device=-1)
+    m = Mm.Mesh(v, e, R.ref_element(3))
+    vM, vP = s.get_maps()
+    assert np.array_equal(vP, m.vmapP)
+    assert np.max(np.abs(s.nodes() - m.x)) <= 1e-14
+
+
+def test_setup_query_sizes_the_workspace():
+    v, e = dginputs.kuhn_cube(4)
+    n64 = P.setup_query(v, e, 4, "f64")
+    n32 = P.setup_query(v, e, 4, "f32")
+    state = 6 * e.shape[0] * 35
+    assert n64 >= 4 * state * 8 and n32 >= 4 * state * 4
+    assert n32 < n64
+
+
+def test_errors_are_reported_not_raised_in_c():
+    v, e = dginputs.kuhn_cube(1)
+    with pytest.raises(P.DGError, match="DG_E_UNSUPPORTED"):
+        P.Solver(v, e, 8, device=-1)
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, np.concatenate([e, e[:1]]), 2, device=-1)
+    bad = e.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, bad, 2, device=-1)
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, np.array([[0, 1, 2, 99]]), 2, device=-1)
+    s = P.Solver(v, e, 2, device=-1)
+    with pytest.raises(P.DGError, match="DG_E_STATE"):
+        s.rk_step(0.01, stream=_NullStream())
+    fb = np.zeros((e.shape[0], 4), dtype=np.int8)
+    fb[0, :] = 1        # a wall on matched faces of element 0 is refused
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, e, 2, device=-1, face_bc=fb)
+
+
+class _NullStream:
+    cuda_stream = 0

@@ -1,0 +1,168 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on seeded inputs.
+
+Tolerances: relative discrete L2 over all fields and nodes, 1e-12 in FP64 and 1e-5 in FP32
+(the FP32 oracle input is the FP32-rounded field cast back to FP64); face maps bit-exact.
+"""
+import numpy as np
+import pytest
+
+import dginputs
+import paper_0901_1024_amd as P
+from gpu_helpers import gpu_rhs, per_field_rel, problem, rel_l2, rounded, say
+from oracle import maxwell as W
+from oracle import mesh as Mm
+from oracle import refelem as R
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def test_cavity_n3_fp64_rhs_and_twenty_steps():
+    """Unit cube 8^3 x 6 = 3072 tets, N = 3, FP64, (1,1,0) TM mode, dt at CFL 0.5, 20 steps."""
+    say("case: cavity N=3 K=3072 f64")
+    v, e, m, u0 = problem(3, 8, fields="cavity")
+    s = P.Solver(v, e, 3, "f64", reorder=1)
+    vM, vP = s.get_maps()
+    assert np.array_equal(vM, m.vmapM) and np.array_equal(vP, m.vmapP)
+    r = gpu_rhs(s, u0)
+    ro = W.rhs(m, u0)
+    assert rel_l2(r, ro) <= TOL["f64"]
+    dt = W.stable_dt(m)
+    assert abs(dt - s.stable_dt(0.5)) <= 1e-15 * dt
+    s.set_fields(u0)
+    e0 = s.energy()
+    assert abs(e0 - W.energy(m, u0)) <= 1e-12 * e0
+    s.solve(dt, 20)
+    ug = s.get_fields()
+    uo, res = u0, None
+    for _ in range(20):
+        uo, res = W.lsrk4_step(m, uo, dt, res)
+    err = rel_l2(ug, uo)
+    say("  rhs rel", rel_l2(r, ro), "20-step rel", err, "per field", per_field_rel(ug, uo))
+    assert err <= TOL["f64"]
+    e20 = s.energy()
+    assert e20 <= e0 * (1 + 1e-14)
+    assert abs(e20 - W.energy(m, uo)) <= 1e-12 * e0
+
+
+@pytest.mark.parametrize("N", range(1, 8))
+def test_all_orders_fp64_jittered_permuted(N):
+    """162 tets (ragged last tile for every order), jittered and permuted, smooth fields."""
+    say(f"case: N={N} K=162 f64 jitter+permute")
+    v, e, m, u0 = problem(N, 3, jitter=0.15, permute=True)
+    s = P.Solver(v, e, N, "f64", reorder=1)
+    assert rel_l2(gpu_rhs(s, u0), W.rhs(m, u0)) <= TOL["f64"]
+    dt = W.stable_dt(m)
+    s.set_fields(u0)
+    s.solve(dt, 3)
+    uo, res = u0, None
+    for _ in range(3):
+        uo, res = W.lsrk4_step(m, uo, dt, res)
+    assert rel_l2(s.get_fields(), uo) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("N", [2, 4, 6])
+def test_fp32_orders_small_mesh(N):
+    say(f"case: N={N} K=384 f32 jitter+permute")
+    v, e, m, u0 = problem(N, 4, jitter=0.15, permute=True)
+    s = P.Solver(v, e, N, "f32", reorder=1)
+    u32 = rounded(u0, "f32")
+    err = rel_l2(gpu_rhs(s, u32), W.rhs(m, u32))
+    say("  rhs rel", err)
+    assert err <= TOL["f32"]
+    dt = W.stable_dt(m)
+    s.set_fields(u32)
+    s.rk_step(dt)
+    uo, _ = W.lsrk4_step(m, u32, dt)
+    assert rel_l2(s.get_fields(), uo) <= TOL["f32"]
+
+
+def test_fp32_full_size_n4_sampled():
+    """6 * 40^3 = 384,000 jittered, permuted tets, N = 4, FP32: the benchmark's workload and
+    launch configuration. The oracle evaluates the right-hand side and one RK step at sampled
+    elements only (dependency cone of the five stages)."""
+    say("case: N=4 K=384000 f32 full size, sampled")
+    v, e, m, u0 = problem(4, 40, jitter=0.15, permute=True, compute_maps=False)
+    s = P.Solver(v, e, 4, "f32", reorder=1)
+    u32 = rounded(u0, "f32")
+    g = np.random.default_rng(11)
+    sample = np.unique(np.concatenate([g.choice(m.K, 1500, replace=False), [0, m.K - 1]]))
+    r = gpu_rhs(s, u32)
+    ro = W.rhs_at(m, u32, sample)
+    err = rel_l2(r[:, sample], ro)
+    say("  sampled rhs rel", err, "per field", per_field_rel(r[:, sample], ro))
+    assert err <= TOL["f32"]
+    dt = W.stable_dt(m)
+    s.set_fields(u32)
+    e0 = s.energy()
+    s.rk_step(dt)
+    ug = s.get_fields()
+    step_sample = sample[:24]
+    uo = W.lsrk4_step_at(m, u32, dt, step_sample)
+    err1 = rel_l2(ug[:, step_sample], uo)
+    say("  sampled 1-step rel", err1)
+    assert err1 <= TOL["f32"]
+    assert s.energy() <= e0 * (1 + 1e-6)
+
+
+def test_reorder_and_repeat_are_bitwise_identical():
+    v, e, m, u0 = problem(4, 3, jitter=0.15, permute=True)
+    a = P.Solver(v, e, 4, "f64", reorder=1)
+    b = P.Solver(v, e, 4, "f64", reorder=0)
+    ra, ra2, rb = gpu_rhs(a, u0), gpu_rhs(a, u0), gpu_rhs(b, u0)
+    assert np.array_equal(ra, ra2)
+    assert np.array_equal(ra, rb)
+    dt = W.stable_dt(m)
+    for s in (a, b):
+        s.set_fields(u0)
+        s.solve(dt, 4)
+    assert np.array_equal(a.get_fields(), b.get_fields())
+
+
+def test_solve_equals_repeated_steps_and_field_round_trip():
+    import torch
+    v, e, m, u0 = problem(3, 2, jitter=0.1, permute=True)
+    s = P.Solver(v, e, 3, "f64")
+    s.set_fields(u0)
+    assert np.array_equal(s.get_fields(), u0)
+    t = torch.from_numpy(u0).cuda()
+    s.set_fields(t)
+    back = torch.empty_like(t)
+    s.get_fields(back)
+    torch.cuda.synchronize()
+    assert torch.equal(back, t)
+    dt = W.stable_dt(m)
+    s.solve(dt, 5)          # two graph replays and one plain step
+    a = s.get_fields()
+    s.set_fields(u0)
+    for _ in range(5):
+        s.rk_step(dt)
+    assert np.array_equal(a, s.get_fields())
+    s.set_fields(u0)
+    s.solve(dt, 2)
+    s.solve(dt, 3)
+    assert np.array_equal(a, s.get_fields())
+
+
+@pytest.mark.parametrize("N", [1, 3, 5, 7])
+def test_degenerate_meshes_single_and_two_tets(N):
+    one_v = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    two_v = np.vstack([one_v, [[0.9, 0.8, 0.95]]])
+    for v, e in ((one_v, np.array([[0, 1, 2, 3]])), (two_v, np.array([[0, 1, 2, 3], [1, 2, 3, 4]]))):
+        m = Mm.Mesh(v, e, R.ref_element(N))
+        x, y, z = m.x
+        u0 = dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), x, y, z)
+        s = P.Solver(v, e, N, "f64")
+        assert rel_l2(gpu_rhs(s, u0), W.rhs(m, u0)) <= TOL["f64"]
+
+
+def test_rhs_rejects_bad_buffers():
+    import torch
+    v, e, m, u0 = problem(2, 1)
+    s = P.Solver(v, e, 2, "f64")
+    t = torch.from_numpy(u0).cuda()
+    with pytest.raises(P.DGError):
+        s.rhs(t, t)          # aliasing input and output
+    with pytest.raises(P.DGError):
+        s.rhs(t.float(), torch.empty_like(t).float())   # wrong precision

@@ -312,3 +312,13 @@ def test_rhs_of_cavity_mode_is_its_time_derivative():
         err, nrm = W.l2_error(m, W.rhs(m, u0), dudt)
         errs.append(err / nrm)
     assert errs[1] < errs[0] / 6.0
+
+
+def test_sampled_rhs_and_step_equal_the_full_ones(small_jittered):
+    _, _, m = small_jittered
+    u = _smooth(m)
+    idx = np.array([0, 5, 17, 40])
+    assert np.array_equal(W.rhs_at(m, u, idx), W.rhs(m, u)[:, idx])
+    dt = W.stable_dt(m)
+    full, _ = W.lsrk4_step(m, u, dt)
+    assert np.array_equal(W.lsrk4_step_at(m, u, dt, idx), full[:, idx])
