@@ -35,12 +35,16 @@ constexpr double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 /
 struct Layout {
   size_t state = 0;  // bytes of one [K][6][Np] array
   size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
-      off_elem_of, off_pos_of, off_partial, total;
+      off_elem_of, off_pos_of, off_partial, off_opcat, total;
+  size_t opcat_bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int K, int Np, int Nfp, size_t ts) {
+// The fragment-ordered concatenated operator is used by the FP32 contraction kernels only.
+int opfrag_words_for(int N, size_t ts) { return (ts == 4 && dgk::mfma_order(N)) ? dgk::opcat_words(N) : 0; }
+
+Layout make_layout(int K, int N, int Np, int Nfp, size_t ts) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -61,6 +65,8 @@ Layout make_layout(int K, int Np, int Nfp, size_t ts) {
   L.off_elem_of = take(size_t(K) * sizeof(int32_t));
   L.off_pos_of = take(size_t(K) * sizeof(int32_t));
   L.off_partial = take(size_t((K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems) * sizeof(double));
+  L.opcat_bytes = size_t(opfrag_words_for(N, ts)) * ts;
+  L.off_opcat = take(L.opcat_bytes);
   L.total = o;
   return L;
 }
@@ -107,6 +113,7 @@ struct dg_handle {
     o.LIFT = at(lay.off_ops + 4 * nn);
     o.fmask = static_cast<const int32_t*>(at(lay.off_fmask));
     o.nbrnode = static_cast<const int32_t*>(at(lay.off_nbr));
+    o.opfrag = lay.opcat_bytes ? at(lay.off_opcat) : nullptr;
     return o;
   }
   void drop_graph() {
@@ -156,6 +163,33 @@ int upload(dg_handle* h, hipStream_t s) {
   for (const auto* m : {&R.Dr, &R.Ds, &R.Dt, &R.M}) ops.insert(ops.end(), m->begin(), m->end());
   ops.insert(ops.end(), R.LIFT.begin(), R.LIFT.end());
   std::vector<char> geo_b = to_prec(geo, h->f64()), ops_b = to_prec(ops, h->f64());
+  if (h->lay.opcat_bytes) {
+    // OpCat = [Dr | Ds | Dt | LIFT], each D block padded to roundup(Np, 4) columns, laid out in
+    // the lane order of the contraction kernel (see dgk::OpsView::opfrag)
+    const int Np = h->Np, npp = (Np + 3) / 4 * 4, KD = 3 * npp + 4 * h->Nfp, KS = KD / 4;
+    const int NT = Np / 16;
+    auto opcat = [&](int n, int k) -> double {
+      if (n >= Np) return 0.0;
+      if (k < 3 * npp) {
+        const int mu = k / npp, j = k % npp;
+        if (j >= Np) return 0.0;
+        const std::vector<double>& Dm = mu == 0 ? R.Dr : mu == 1 ? R.Ds : R.Dt;
+        return Dm[size_t(n) * Np + j];
+      }
+      return R.LIFT[size_t(n) * 4 * h->Nfp + (k - 3 * npp)];
+    };
+    std::vector<double> oc(size_t(opfrag_words_for(h->N, h->ts)), 0.0);
+    size_t w = 0;
+    for (int nt = 0; nt < NT; ++nt)
+      for (int kk = 0; kk < KS; ++kk)
+        for (int lane = 0; lane < 64; ++lane) oc[w++] = opcat(16 * nt + lane % 16, 4 * kk + lane / 16);
+    for (int k = 0; k < KD; ++k)
+      for (int c = 0; c < 4; ++c) oc[w++] = opcat(16 * NT + c, k);
+    if (w != oc.size()) return fail(DG_E_ARG, "internal: operator fragment size mismatch");
+    std::vector<char> oc_b = to_prec(oc, h->f64());
+    HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_opcat), oc_b.data(), oc_b.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_geo), geo_b.data(), geo_b.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_ops), ops_b.data(), ops_b.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_fcode), M.face_code.data(), M.face_code.size() * 4,
@@ -220,7 +254,7 @@ int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_b
   if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
   const int N = opts->order;
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
-  *workspace_bytes = make_layout(mesh->K, Np, Nfp, opts->precision == DG_F64 ? 8 : 4).total;
+  *workspace_bytes = make_layout(mesh->K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4).total;
   return DG_OK;
 }
 
@@ -248,7 +282,7 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
   h->prec = opts->precision;
   h->ts = h->f64() ? 8 : 4;
   h->device = opts->device;
-  h->lay = make_layout(h->K, h->Np, h->Nfp, h->ts);
+  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts);
   if (h->device >= 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());

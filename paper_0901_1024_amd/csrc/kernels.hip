@@ -147,6 +147,290 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// MFMA form of the fused stage (FP32).
+//
+// Because the inverse-map derivatives are constant per element, the curl can be taken before
+// differentiating (the freedom to commute F(u) with the local differentiation noted in
+// Sec. 4): with c[mu][nu] = d r_mu / d x_nu,
+//   (curl H)_a = sum_mu D_mu (c[mu][b] H_c - c[mu][c] H_b),  (a,b,c) cyclic,
+// and likewise -(curl E)_a. Volume and surface terms then form one contraction per element
+// and field:  rhs = [Dr | Ds | Dt | LIFT] * [G_r; G_s; G_t; Fscale/2 * flux],
+// an (Np x KD) operator times a (KD x 6E) operand, for a tile of E elements.
+//
+// Orientation: rows = (field, element) pairs, columns = nodes, so each result row lands on
+// consecutive nodes. Full 16-node column tiles run on v_mfma_f32_16x16x4f32 with the
+// operator fragments held in VGPRs; the remaining Np mod 16 columns run on
+// v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns). The volume part of the operand is
+// formed on the fly from the field tile in LDS (two LDS reads and two FMAs per value); only
+// the face-flux part is materialised, which keeps LDS near 40 KB and four workgroups per CU.
+
+template <int N>
+struct MDims {
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, Nf4 = Dims<N>::Nf4;
+  static constexpr int E = 16;                       // elements per tile
+  static constexpr int ROWS = 6 * E;                 // (field, element) rows, field-major
+  static constexpr int NPP = (Np + 3) / 4 * 4;       // volume block per direction, padded
+  static constexpr int KV = 3 * NPP;                 // volume part of the contraction
+  static constexpr int KD = KV + Nf4;                // contraction length (multiple of 4)
+  static constexpr int KS = KD / 4;                  // k-steps; lane group g takes k = 4 kk + g
+  static constexpr int RSL = Nf4 + 2;                // flux row stride, = 2 mod 4 (no bank conflicts)
+  static constexpr int NT = Np / 16;                 // full 16-node column tiles
+  static constexpr int TAIL = Np - 16 * NT;          // columns left for the 4x4 blocks
+  static constexpr int RT = ROWS / 16;               // 16-row tiles (one field each)
+  static constexpr int TILES = RT * NT;              // dealt round-robin to the four waves
+  static constexpr int TPW = (TILES + 3) / 4;
+  static constexpr int RG = TAIL > 0 ? (ROWS + 63) / 64 : 0;   // 64-row groups of the tail
+  static constexpr int FIT = (E * Nf4 + kThreads - 1) / kThreads;  // face nodes per thread
+  // fragment-ordered operator: NT * KS * 64 floats, then the tail columns as [KD][4]
+  static constexpr int OPC = NT * KS * 64 + KD * 4;
+  static_assert(NT == 1 || NT == 2 || NT == 4, "a wave's tiles must share one column tile");
+  static_assert(RG <= 4 && TAIL <= 4, "tail must fit one 4-column block per row group");
+};
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int N, bool STAGE>
+__global__ __launch_bounds__(kThreads) void mfma_stage_kernel(
+    const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
+    const float* __restrict__ geo, const int32_t* __restrict__ fcode,
+    const float* __restrict__ opf, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
+  using D = MDims<N>;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, KV = D::KV,
+                KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT, TAIL = D::TAIL,
+                TILES = D::TILES, TPW = D::TPW, RG = D::RG, FIT = D::FIT;
+  constexpr int G = dgh::kGeoStride;
+  __shared__ __align__(16) float us[E * 6 * NP];   // field tile [e][f][n]
+  __shared__ float gl[D::ROWS * RSL];    // Fscale/2 * flux, [f E + e][fj]
+  __shared__ float gt[E * G];            // geometric records of the tile
+  __shared__ int32_t fc[E * 4];          // face records of the tile
+  __shared__ uint8_t nbr_s[96 * NFP];    // neighbour node table
+  __shared__ uint8_t fm_s[4 * NFP];      // face node lists
+
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= ntiles) return;
+  const int base = tile * E;
+  const int nel = min(E, K - base);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
+  const int g4 = lane >> 4, li = lane & 15;
+
+  // operator fragments of this wave's column tile: lane holds OpCat[16 nt + li][4 kk + g4]
+  const int nt = wave % NT;
+  float bf[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) bf[kk] = opf[(nt * KS + kk) * 64 + lane];
+
+  {
+    const float* src = u_in + size_t(base) * 6 * NP;
+    const int nv = nel * 6 * NP;
+    if (nel == E) {   // a full tile is 16-byte aligned: 16 * 6 * Np floats from a multiple of 16
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      for (int q = tid; q < nv / 4; q += kThreads) reinterpret_cast<float4*>(us)[q] = s4[q];
+    } else {
+      for (int q = tid; q < nv; q += kThreads) us[q] = src[q];
+    }
+    for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
+    for (int q = tid; q < nel * 4; q += kThreads) fc[q] = fcode[size_t(base) * 4 + q];
+    for (int q = tid; q < 96 * NFP; q += kThreads) nbr_s[q] = uint8_t(nbrnode[q]);
+    for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
+  }
+  __syncthreads();
+
+  // ---- face fluxes: fetch every neighbour trace first, then compute
+  {
+    float up[FIT][6];
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = tid + r * kThreads;
+      if (q < nel * NF4) {
+        const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+        const int code = fc[e * 4 + f];
+        if (code >= 0) {
+          const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
+          const int nn = nbr_s[((f * 4 + f2) * 6 + o) * NFP + j];
+          const int le = nb - base;
+          const float* p = (le >= 0 && le < nel) ? us + le * 6 * NP + nn : u_in + size_t(nb) * 6 * NP + nn;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = tid + r * kThreads;
+      if (q < nel * NF4) {
+        const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+        const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+        const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
+        const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
+        const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
+        float dEx, dEy, dEz, dHx, dHy, dHz;
+        if (fc[e * 4 + f] < 0) {   // perfectly conducting wall: E+ = -E-, H+ = H-
+          dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
+          dHx = dHy = dHz = 0.f;
+        } else {
+          dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
+          dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
+        }
+        const float ndE = nx * dEx + ny * dEy + nz * dEz;
+        const float ndH = nx * dHx + ny * dHy + nz * dHz;
+        float* o = gl + e * RSL + fj;
+        o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
+        o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
+        o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
+        o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
+        o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
+        o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li)
+  floatx4 acc[TPW];
+  float pc[TPW][3], qc[TPW][3];   // operand = pc[mu] * V_c[j] + qc[mu] * V_b[j]
+  const float* vc[TPW];
+  const float* vb[TPW];
+  const float* fl[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int tt = min(wave + 4 * t, TILES - 1);
+    const int f = tt / NT;
+    const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+    const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
+    const float sg = f < 3 ? 1.f : -1.f;
+    const float* cm = gt + li * G;
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      pc[t][mu] = sg * cm[3 * mu + b];
+      qc[t][mu] = -sg * cm[3 * mu + c];
+    }
+    vc[t] = us + li * 6 * NP + (srcf + c) * NP + g4;
+    vb[t] = us + li * 6 * NP + (srcf + b) * NP + g4;
+    fl[t] = gl + (f * E + li) * RSL + g4;
+  }
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    // branch-free: a wave with fewer than TPW tiles repeats its last one and drops the result
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      float av;
+      if (4 * kk < KV) {
+        const int mu = (4 * kk) / NPP, j0 = 4 * kk - mu * NPP;
+        if (j0 + 3 < NP) {
+          av = pc[t][mu] * vc[t][j0] + qc[t][mu] * vb[t][j0];
+        } else {   // last block of a direction: columns j >= Np are zero padding
+          const int jj = min(j0, NP - 1 - g4);
+          const float v = pc[t][mu] * vc[t][jj] + qc[t][mu] * vb[t][jj];
+          av = (j0 + g4 < NP) ? v : 0.f;
+        }
+      } else {
+        av = fl[t][4 * kk - KV];
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[kk], acc[t], 0, 0, 0);
+    }
+  }
+  // epilogue: lane holds rows 4 g4 + i (elements) of its field, node 16 nt + li
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tt = wave + 4 * t;
+    if (tt >= TILES) continue;
+    const int f = tt / NT;
+    const int n = 16 * nt + li;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = 4 * g4 + i;
+      if (e < nel) {
+        const size_t idx = (size_t(base + e) * 6 + f) * NP + n;
+        if (STAGE) {
+          const float rv = ca * res[idx] + cdt * acc[t][i];
+          res[idx] = rv;
+          out[idx] = us[(e * 6 + f) * NP + n] + cb * rv;
+        } else {
+          out[idx] = acc[t][i];
+        }
+      }
+    }
+  }
+
+  // ---- tail columns 16 NT .. Np-1: v_mfma_f32_4x4x1f32, one 64-row group per wave
+  if (TAIL > 0 && wave < RG) {
+    const int row = 64 * wave + lane;
+    const bool rowok = row < D::ROWS;
+    const int f = rowok ? row / E : 0, e = row - (row / E) * E;
+    const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+    const int srcf = f < 3 ? 3 : 0;
+    const float sg = rowok ? (f < 3 ? 1.f : -1.f) : 0.f;
+    const float* cm = gt + e * G;
+    float pt[3], qt[3];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      pt[mu] = sg * cm[3 * mu + b];
+      qt[mu] = -sg * cm[3 * mu + c];
+    }
+    const float* tvc = us + e * 6 * NP + (srcf + c) * NP;
+    const float* tvb = us + e * 6 * NP + (srcf + b) * NP;
+    const float* tfl = gl + (rowok ? row : 0) * RSL;
+    const float* top = opf + NT * KS * 64 + (lane & 3);
+    floatx4 tacc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+      float av;
+      if (k < KV) {
+        const int mu = k / NPP, j = k - mu * NPP;
+        av = (j < NP) ? pt[mu] * tvc[j] + qt[mu] * tvb[j] : 0.f;
+      } else {
+        av = rowok ? tfl[k - KV] : 0.f;
+      }
+      tacc = __builtin_amdgcn_mfma_f32_4x4x1f32(av, top[4 * k], tacc, 0, 0, 0);
+    }
+    // lane (block, column): rows 64 wave + 4 block + i, node 16 NT + column
+    const int col = lane & 3, blk = lane >> 2;
+    if (col < TAIL) {
+      const int n = 16 * NT + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r2 = 64 * wave + 4 * blk + i;
+        if (r2 < D::ROWS) {
+          const int f2 = r2 / E, e2 = r2 - f2 * E;
+          if (e2 < nel) {
+            const size_t idx = (size_t(base + e2) * 6 + f2) * NP + n;
+            if (STAGE) {
+              const float rv = ca * res[idx] + cdt * tacc[i];
+              res[idx] = rv;
+              out[idx] = us[(e2 * 6 + f2) * NP + n] + cb * rv;
+            } else {
+              out[idx] = tacc[i];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_mfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const int E = MDims<N>::E;
+  const int ntiles = (a.K + E - 1) / E;
+  const int nblocks = ((ntiles + kXcds - 1) / kXcds) * kXcds;
+  auto* u = static_cast<const float*>(a.u_in);
+  auto* o = static_cast<float*>(a.out);
+  auto* r = static_cast<float*>(a.res);
+  auto* g = static_cast<const float*>(a.geo);
+  auto* oc = static_cast<const float*>(ops.opfrag);
+  if (stage)
+    mfma_stage_kernel<N, true><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
+                                                           a.K, ntiles, float(a.a), float(a.b), float(a.dt));
+  else
+    mfma_stage_kernel<N, false><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
+                                                            a.K, ntiles, 0.f, 0.f, 0.f);
+  return hipGetLastError();
+}
+
 template <typename T, int N>
 hipError_t launch_stage_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = Dims<N>::E;
@@ -270,6 +554,16 @@ int grid_for(int64_t total) {
 
 }  // namespace
 
+int opcat_words(int N) {
+  switch (N) {
+    case 3: return MDims<3>::OPC;
+    case 4: return MDims<4>::OPC;
+  }
+  return 0;
+}
+
+bool mfma_order(int N) { return N == 3 || N == 4; }
+
 int tile_elems(int N) {
   switch (N) {
     case 1: return Dims<1>::E;
@@ -285,6 +579,10 @@ int tile_elems(int N) {
 
 hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
                         hipStream_t s) {
+  if (!f64 && ops.opfrag) {
+    if (N == 3) return launch_mfma_t<3>(stage, ops, a, s);
+    if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);
+  }
   return f64 ? dispatch_stage<double>(N, stage, ops, a, s) : dispatch_stage<float>(N, stage, ops, a, s);
 }
 

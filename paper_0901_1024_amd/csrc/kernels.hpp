@@ -16,7 +16,18 @@ struct OpsView {
   const void* M;
   const int32_t* fmask;    // 4 x Nfp
   const int32_t* nbrnode;  // 4 x 4 x 6 x Nfp
+  // The concatenated operator OpCat = [Dr | Ds | Dt | LIFT] (Np x KD, each D block
+  // zero-padded to roundup(Np, 4) columns, KD = 3 roundup(Np, 4) + 4 Nfp) in MFMA fragment
+  // order (FP32 contraction kernels only; NULL where unused):
+  //   [nt][kk][lane] = OpCat[16 nt + lane % 16][4 kk + lane / 16]  for the full 16-node tiles,
+  //   then [k][c]    = OpCat[16 NT + c][k] (zero for rows >= Np)    for the remaining nodes.
+  const void* opfrag;
 };
+
+// Floats in the fragment-ordered operator for order N (0 when no contraction kernel serves N).
+int opcat_words(int N);
+// Whether the FP32 MFMA stage kernel serves order N.
+bool mfma_order(int N);
 
 struct StageArgs {
   const void* u_in;  // internal layout [K][6][Np]

@@ -62,10 +62,11 @@ def test_all_orders_fp64_jittered_permuted(N):
     assert rel_l2(s.get_fields(), uo) <= TOL["f64"]
 
 
-@pytest.mark.parametrize("N", [2, 4, 6])
-def test_fp32_orders_small_mesh(N):
-    say(f"case: N={N} K=384 f32 jitter+permute")
-    v, e, m, u0 = problem(N, 4, jitter=0.15, permute=True)
+@pytest.mark.parametrize("N,n", [(2, 3), (3, 3), (4, 3), (4, 4), (6, 3)])
+def test_fp32_orders_small_mesh(N, n):
+    """K = 162 leaves a ragged last tile of every tile size; K = 384 fills them."""
+    say(f"case: N={N} K={6 * n ** 3} f32 jitter+permute")
+    v, e, m, u0 = problem(N, n, jitter=0.15, permute=True)
     s = P.Solver(v, e, N, "f32", reorder=1)
     u32 = rounded(u0, "f32")
     err = rel_l2(gpu_rhs(s, u32), W.rhs(m, u32))
