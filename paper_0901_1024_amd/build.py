@@ -34,9 +34,10 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), "-c", src, "-o", obj] + COMMON
     if src.endswith(".hip"):
         cmd = [hipcc(), "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE_FLAGS
+    else:   # host-only C++ (the HIP runtime API headers need only the platform macro)
+        cmd = ["g++", "-c", src, "-o", obj, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"] + COMMON
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -117,8 +117,8 @@ struct dg_handle {
     return o;
   }
   void drop_graph() {
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (graph) hipGraphDestroy(graph);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
     gexec = nullptr;
     graph = nullptr;
     graph_cur = -1;
@@ -301,12 +301,12 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
     }
     rc = upload(h.get(), s);
     if (rc) {
-      if (h->own_ws) hipFree(h->ws);
+      if (h->own_ws) (void)hipFree(h->ws);
       return rc;
     }
     hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
-      if (h->own_ws) hipFree(h->ws);
+      if (h->own_ws) (void)hipFree(h->ws);
       return hip_fail(e, "hipStreamCreateWithFlags");
     }
   }
@@ -317,10 +317,10 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
 int dg_free(dg_handle* h) {
   if (!h) return DG_OK;
   if (h->device >= 0) {
-    hipSetDevice(h->device);
+    (void)hipSetDevice(h->device);
     h->drop_graph();
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
-    if (h->own_ws && h->ws) hipFree(h->ws);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
   }
   delete h;
   return DG_OK;
@@ -448,7 +448,7 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
       hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
       h->cur = saved;
       if (r2) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return r2;
       }
       if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");

@@ -170,6 +170,9 @@ struct MDims {
   static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, Nf4 = Dims<N>::Nf4;
   static constexpr int E = 16;                       // elements per tile
   static constexpr int ROWS = 6 * E;                 // (field, element) rows, field-major
+  static constexpr int TW = E * 6 * Np;              // words in a tile of fields
+  static constexpr int TW4 = TW / 4;                 // float4 chunks in a tile
+  static constexpr int CPT = (TW4 + kThreads - 1) / kThreads;   // float4 chunks per thread
   static constexpr int NPP = (Np + 3) / 4 * 4;       // volume block per direction, padded
   static constexpr int KV = 3 * NPP;                 // volume part of the contraction
   static constexpr int KD = KV + Nf4;                // contraction length (multiple of 4)
@@ -185,13 +188,16 @@ struct MDims {
   // fragment-ordered operator: NT * KS * 64 floats, then the tail columns as [KD][4]
   static constexpr int OPC = NT * KS * 64 + KD * 4;
   static_assert(NT == 1 || NT == 2 || NT == 4, "a wave's tiles must share one column tile");
-  static_assert(RG <= 4 && TAIL <= 4, "tail must fit one 4-column block per row group");
+  static_assert(RG <= 2 && TAIL <= 4, "tail must fit one 4-column block per row group");
+  static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
+  // after the contraction the flux rows are free: rhs staging [e][f][n] and tail partials
+  static_assert(TW + 4 * RG * 256 <= ROWS * RSL, "staging must fit in the flux rows");
 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int N, bool STAGE>
-__global__ __launch_bounds__(kThreads) void mfma_stage_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void mfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
     const float* __restrict__ geo, const int32_t* __restrict__ fcode,
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
@@ -199,235 +205,358 @@ __global__ __launch_bounds__(kThreads) void mfma_stage_kernel(
   using D = MDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, KV = D::KV,
                 KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT, TAIL = D::TAIL,
-                TILES = D::TILES, TPW = D::TPW, RG = D::RG, FIT = D::FIT;
+                TILES = D::TILES, TPW = D::TPW, RG = D::RG, FIT = D::FIT, TW = D::TW,
+                TW4 = D::TW4, CPT = D::CPT;
   constexpr int G = dgh::kGeoStride;
-  __shared__ __align__(16) float us[E * 6 * NP];   // field tile [e][f][n]
-  __shared__ float gl[D::ROWS * RSL];    // Fscale/2 * flux, [f E + e][fj]
-  __shared__ float gt[E * G];            // geometric records of the tile
-  __shared__ int32_t fc[E * 4];          // face records of the tile
-  __shared__ uint8_t nbr_s[96 * NFP];    // neighbour node table
-  __shared__ uint8_t fm_s[4 * NFP];      // face node lists
+  constexpr int GW = E * G;                                   // words of geometry per tile
+  constexpr int GPT = (GW + kThreads - 1) / kThreads;
+  __shared__ __align__(16) float us[TW];              // field tile [e][f][n]
+  __shared__ __align__(16) float gl[D::ROWS * RSL];   // Fscale/2 * flux [f E + e][fj]; later staging
+  __shared__ float gt[GW];                            // geometric records of the tile
+  __shared__ float tops[TAIL > 0 ? KD * 4 : 4];       // operator columns of the tail, [k][c]
+  __shared__ int32_t fc[E * 4];                       // face records of the tile
+  __shared__ uint8_t nbr_s[96 * NFP];                 // neighbour node table
+  __shared__ uint8_t fm_s[4 * NFP];                   // face node lists
+  __shared__ float bfs[NT * KS * 64];                 // operator fragments, [nt][kk][lane]
 
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= ntiles) return;
-  const int base = tile * E;
-  const int nel = min(E, K - base);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
   const int g4 = lane >> 4, li = lane & 15;
 
-  // operator fragments of this wave's column tile: lane holds OpCat[16 nt + li][4 kk + g4]
+  // Persistent schedule: workgroups are dispatched round-robin over the XCDs; XCD x owns the
+  // contiguous tile range [x TX, (x+1) TX) and its workgroups sweep it together, so at any time
+  // an XCD works on one window of neighbouring tiles (shared L2 for the neighbour traces).
+  const int nwg = gridDim.x / kXcds;                 // workgroups per XCD (grid is a multiple of 8)
+  const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
+  const int TX = (ntiles + kXcds - 1) / kXcds;
+  const int tend = min(ntiles, (xcd + 1) * TX);
+  int tile = xcd * TX + wj;
+  if (tile >= tend) return;
+
+  // once per workgroup: operator fragments, node tables, tail operator
   const int nt = wave % NT;
-  float bf[KS];
-#pragma unroll
-  for (int kk = 0; kk < KS; ++kk) bf[kk] = opf[(nt * KS + kk) * 64 + lane];
+  for (int q = tid; q < NT * KS * 64; q += kThreads) bfs[q] = opf[q];
+  const float* bf = bfs + nt * KS * 64 + lane;   // lane's fragment of k-step kk at bf[64 kk]
+  for (int q = tid; q < 96 * NFP; q += kThreads) nbr_s[q] = uint8_t(nbrnode[q]);
+  for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
+  if (TAIL > 0)
+    for (int q = tid; q < KD * 4; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
 
-  {
-    const float* src = u_in + size_t(base) * 6 * NP;
-    const int nv = nel * 6 * NP;
-    if (nel == E) {   // a full tile is 16-byte aligned: 16 * 6 * Np floats from a multiple of 16
-      const float4* s4 = reinterpret_cast<const float4*>(src);
-      for (int q = tid; q < nv / 4; q += kThreads) reinterpret_cast<float4*>(us)[q] = s4[q];
+  // prefetch registers: fields, geometry and face records of the next tile
+  float4 pu[CPT];
+  float pg[GPT];
+  int32_t pf = 0;
+  auto prefetch = [&](int t) {
+    if (t * E + E <= K) {   // full tiles only; a ragged tile is read directly
+      const float4* s4 = reinterpret_cast<const float4*>(u_in + size_t(t) * E * 6 * NP);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < TW4) pu[r] = s4[q];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < GW) pg[r] = geo[size_t(t) * GW + q];
+      }
+      if (tid < E * 4) pf = fcode[size_t(t) * E * 4 + tid];
+    }
+  };
+  prefetch(tile);
+
+  for (; tile < tend; tile += nwg) {
+    const int base = tile * E;
+    const int nel = min(E, K - base);
+    const bool full = nel == E;   // a full tile is 16-byte aligned in every [K][6][Np] array
+    const size_t tb = size_t(base) * 6 * NP;
+
+    // ---- tile into LDS (from the prefetch registers when full)
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < TW4) reinterpret_cast<float4*>(us)[q] = pu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < GW) gt[q] = pg[r];
+      }
+      if (tid < E * 4) fc[tid] = pf;
     } else {
-      for (int q = tid; q < nv; q += kThreads) us[q] = src[q];
+      for (int q = tid; q < nel * 6 * NP; q += kThreads) us[q] = u_in[tb + q];
+      for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
+      for (int q = tid; q < nel * 4; q += kThreads) fc[q] = fcode[size_t(base) * 4 + q];
     }
-    for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
-    for (int q = tid; q < nel * 4; q += kThreads) fc[q] = fcode[size_t(base) * 4 + q];
-    for (int q = tid; q < 96 * NFP; q += kThreads) nbr_s[q] = uint8_t(nbrnode[q]);
-    for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // ---- face fluxes: fetch every neighbour trace first, then compute
-  {
-    float up[FIT][6];
+    // ---- issue the loads the rest of this tile and the next tile will need
+    float4 rs4[CPT];
+    if (STAGE && full) {
 #pragma unroll
-    for (int r = 0; r < FIT; ++r) {
-      const int q = tid + r * kThreads;
-      if (q < nel * NF4) {
-        const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
-        const int code = fc[e * 4 + f];
-        if (code >= 0) {
-          const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
-          const int nn = nbr_s[((f * 4 + f2) * 6 + o) * NFP + j];
-          const int le = nb - base;
-          const float* p = (le >= 0 && le < nel) ? us + le * 6 * NP + nn : u_in + size_t(nb) * 6 * NP + nn;
-#pragma unroll
-          for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
-        }
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < TW4) rs4[r] = reinterpret_cast<const float4*>(res + tb)[q];
       }
     }
-#pragma unroll
-    for (int r = 0; r < FIT; ++r) {
-      const int q = tid + r * kThreads;
-      if (q < nel * NF4) {
-        const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
-        const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
-        const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
-        const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
-        const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
-        float dEx, dEy, dEz, dHx, dHy, dHz;
-        if (fc[e * 4 + f] < 0) {   // perfectly conducting wall: E+ = -E-, H+ = H-
-          dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
-          dHx = dHy = dHz = 0.f;
-        } else {
-          dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
-          dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
-        }
-        const float ndE = nx * dEx + ny * dEy + nz * dEz;
-        const float ndH = nx * dHx + ny * dHy + nz * dHz;
-        float* o = gl + e * RSL + fj;
-        o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
-        o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
-        o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
-        o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
-        o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
-        o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
-      }
-    }
-  }
-  __syncthreads();
+    if (tile + nwg < tend) prefetch(tile + nwg);
 
-  // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li)
-  floatx4 acc[TPW];
-  float pc[TPW][3], qc[TPW][3];   // operand = pc[mu] * V_c[j] + qc[mu] * V_b[j]
-  const float* vc[TPW];
-  const float* vb[TPW];
-  const float* fl[TPW];
+    // ---- face fluxes: fetch every neighbour trace first, then compute
+    {
+      float up[FIT][6];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int tt = min(wave + 4 * t, TILES - 1);
-    const int f = tt / NT;
-    const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
-    const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
-    const float sg = f < 3 ? 1.f : -1.f;
-    const float* cm = gt + li * G;
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          const int code = fc[e * 4 + f];
+          if (code >= 0) {
+            const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
+            const int nn = nbr_s[((f * 4 + f2) * 6 + o) * NFP + j];
+            const int le = nb - base;
+            if (le >= 0 && le < nel) {
+              const float* p = us + le * 6 * NP + nn;
 #pragma unroll
-    for (int mu = 0; mu < 3; ++mu) {
-      pc[t][mu] = sg * cm[3 * mu + b];
-      qc[t][mu] = -sg * cm[3 * mu + c];
-    }
-    vc[t] = us + li * 6 * NP + (srcf + c) * NP + g4;
-    vb[t] = us + li * 6 * NP + (srcf + b) * NP + g4;
-    fl[t] = gl + (f * E + li) * RSL + g4;
-  }
-#pragma unroll
-  for (int kk = 0; kk < KS; ++kk) {
-    // branch-free: a wave with fewer than TPW tiles repeats its last one and drops the result
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      float av;
-      if (4 * kk < KV) {
-        const int mu = (4 * kk) / NPP, j0 = 4 * kk - mu * NPP;
-        if (j0 + 3 < NP) {
-          av = pc[t][mu] * vc[t][j0] + qc[t][mu] * vb[t][j0];
-        } else {   // last block of a direction: columns j >= Np are zero padding
-          const int jj = min(j0, NP - 1 - g4);
-          const float v = pc[t][mu] * vc[t][jj] + qc[t][mu] * vb[t][jj];
-          av = (j0 + g4 < NP) ? v : 0.f;
-        }
-      } else {
-        av = fl[t][4 * kk - KV];
-      }
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[kk], acc[t], 0, 0, 0);
-    }
-  }
-  // epilogue: lane holds rows 4 g4 + i (elements) of its field, node 16 nt + li
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tt = wave + 4 * t;
-    if (tt >= TILES) continue;
-    const int f = tt / NT;
-    const int n = 16 * nt + li;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = 4 * g4 + i;
-      if (e < nel) {
-        const size_t idx = (size_t(base + e) * 6 + f) * NP + n;
-        if (STAGE) {
-          const float rv = ca * res[idx] + cdt * acc[t][i];
-          res[idx] = rv;
-          out[idx] = us[(e * 6 + f) * NP + n] + cb * rv;
-        } else {
-          out[idx] = acc[t][i];
-        }
-      }
-    }
-  }
-
-  // ---- tail columns 16 NT .. Np-1: v_mfma_f32_4x4x1f32, one 64-row group per wave
-  if (TAIL > 0 && wave < RG) {
-    const int row = 64 * wave + lane;
-    const bool rowok = row < D::ROWS;
-    const int f = rowok ? row / E : 0, e = row - (row / E) * E;
-    const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
-    const int srcf = f < 3 ? 3 : 0;
-    const float sg = rowok ? (f < 3 ? 1.f : -1.f) : 0.f;
-    const float* cm = gt + e * G;
-    float pt[3], qt[3];
-#pragma unroll
-    for (int mu = 0; mu < 3; ++mu) {
-      pt[mu] = sg * cm[3 * mu + b];
-      qt[mu] = -sg * cm[3 * mu + c];
-    }
-    const float* tvc = us + e * 6 * NP + (srcf + c) * NP;
-    const float* tvb = us + e * 6 * NP + (srcf + b) * NP;
-    const float* tfl = gl + (rowok ? row : 0) * RSL;
-    const float* top = opf + NT * KS * 64 + (lane & 3);
-    floatx4 tacc = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < KD; ++k) {
-      float av;
-      if (k < KV) {
-        const int mu = k / NPP, j = k - mu * NPP;
-        av = (j < NP) ? pt[mu] * tvc[j] + qt[mu] * tvb[j] : 0.f;
-      } else {
-        av = rowok ? tfl[k - KV] : 0.f;
-      }
-      tacc = __builtin_amdgcn_mfma_f32_4x4x1f32(av, top[4 * k], tacc, 0, 0, 0);
-    }
-    // lane (block, column): rows 64 wave + 4 block + i, node 16 NT + column
-    const int col = lane & 3, blk = lane >> 2;
-    if (col < TAIL) {
-      const int n = 16 * NT + col;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r2 = 64 * wave + 4 * blk + i;
-        if (r2 < D::ROWS) {
-          const int f2 = r2 / E, e2 = r2 - f2 * E;
-          if (e2 < nel) {
-            const size_t idx = (size_t(base + e2) * 6 + f2) * NP + n;
-            if (STAGE) {
-              const float rv = ca * res[idx] + cdt * tacc[i];
-              res[idx] = rv;
-              out[idx] = us[(e2 * 6 + f2) * NP + n] + cb * rv;
+              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
             } else {
-              out[idx] = tacc[i];
+              const float* p = u_in + size_t(nb) * 6 * NP + nn;
+#pragma unroll
+              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
             }
           }
         }
       }
+#pragma unroll
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+          const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
+          const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
+          const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
+          float dEx, dEy, dEz, dHx, dHy, dHz;
+          if (fc[e * 4 + f] < 0) {   // perfectly conducting wall: E+ = -E-, H+ = H-
+            dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
+            dHx = dHy = dHz = 0.f;
+          } else {
+            dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
+            dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
+          }
+          const float ndE = nx * dEx + ny * dEy + nz * dEz;
+          const float ndH = nx * dHx + ny * dHy + nz * dHz;
+          float* o = gl + e * RSL + fj;
+          o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
+          o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
+          o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
+          o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
+          o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
+          o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+        }
+      }
     }
+    __syncthreads();
+
+    // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li)
+    floatx4 acc[TPW];
+    {
+      float pc[TPW][3], qc[TPW][3];   // operand = pc[mu] * V_c[j] + qc[mu] * V_b[j]
+      const float* vc[TPW];
+      const float* vb[TPW];
+      const float* fl[TPW];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int tt = min(wave + 4 * t, TILES - 1);
+        const int f = tt / NT;
+        const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+        const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
+        const float sg = f < 3 ? 1.f : -1.f;
+        const float* cm = gt + li * G;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          pc[t][mu] = sg * cm[3 * mu + b];
+          qc[t][mu] = -sg * cm[3 * mu + c];
+        }
+        vc[t] = us + li * 6 * NP + (srcf + c) * NP + g4;
+        vb[t] = us + li * 6 * NP + (srcf + b) * NP + g4;
+        fl[t] = gl + (f * E + li) * RSL + g4;
+      }
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        // branch-free: a wave with fewer than TPW tiles repeats its last one and drops the result
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          float av;
+          if (4 * kk < KV) {
+            const int mu = (4 * kk) / NPP, j0 = 4 * kk - mu * NPP;
+            if (j0 + 3 < NP) {
+              av = pc[t][mu] * vc[t][j0] + qc[t][mu] * vb[t][j0];
+            } else {   // last block of a direction: columns j >= Np are zero padding
+              const int jj = min(j0, NP - 1 - g4);
+              const float v = pc[t][mu] * vc[t][jj] + qc[t][mu] * vb[t][jj];
+              av = (j0 + g4 < NP) ? v : 0.f;
+            }
+          } else {
+            av = fl[t][4 * kk - KV];
+          }
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[64 * kk], acc[t], 0, 0, 0);
+        }
+      }
+    }
+
+    // ---- tail columns 16 NT .. Np-1 on v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns):
+    // every wave takes the k = wave (mod 4) quarter of both row groups; partial sums meet in LDS
+    floatx4 tacc[RG > 0 ? RG : 1][2];
+    if (TAIL > 0) {
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) {
+        tacc[rg][0] = tacc[rg][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int row = 64 * rg + lane;
+        const bool rowok = row < D::ROWS;
+        const int f = rowok ? row / E : 0, e = row - (row / E) * E;
+        const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+        const int srcf = f < 3 ? 3 : 0;
+        const float sg = rowok ? (f < 3 ? 1.f : -1.f) : 0.f;
+        const float* cm = gt + e * G;
+        float pt[3], qt[3];
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          pt[mu] = sg * cm[3 * mu + b];
+          qt[mu] = -sg * cm[3 * mu + c];
+        }
+        const float* tvc = us + e * 6 * NP + (srcf + c) * NP + wave;
+        const float* tvb = us + e * 6 * NP + (srcf + b) * NP + wave;
+        const float* tfl = gl + (rowok ? row : 0) * RSL + wave;
+        const float* top = tops + 4 * wave + (lane & 3);
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {   // k = 4 kk + wave
+          float av;
+          if (4 * kk < KV) {
+            const int mu = (4 * kk) / NPP, j0 = 4 * kk - mu * NPP;
+            if (j0 + 3 < NP) {
+              av = pt[mu] * tvc[j0] + qt[mu] * tvb[j0];
+            } else {
+              const int jj = min(j0, NP - 1 - wave);
+              const float v = pt[mu] * tvc[jj] + qt[mu] * tvb[jj];
+              av = (j0 + wave < NP) ? v : 0.f;
+            }
+          } else {
+            av = rowok ? tfl[4 * kk - KV] : 0.f;
+          }
+          tacc[rg][kk & 1] = __builtin_amdgcn_mfma_f32_4x4x1f32(av, top[16 * kk], tacc[rg][kk & 1], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();   // flux rows are read: reuse them for the staging
+
+    // ---- stage the right-hand side [e][f][n] in LDS
+    float* stage = gl;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tt = wave + 4 * t;
+      if (tt < TILES) {
+        const int f = tt / NT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) stage[((4 * g4 + i) * 6 + f) * NP + 16 * nt + li] = acc[t][i];
+      }
+    }
+    if (TAIL > 0) {
+      float* part = gl + TW;   // [wave][rg][i][lane]
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[((wave * RG + rg) * 4 + i) * 64 + lane] = tacc[rg][0][i] + tacc[rg][1][i];
+      __syncthreads();
+      // lane (block, column) of row group rg holds rows 64 rg + 4 block + i, node 16 NT + column
+      for (int q = tid; q < RG * 4 * 64; q += kThreads) {
+        const int rg = q / 256, i = (q / 64) % 4, ln = q % 64;
+        const int col = ln & 3, row = 64 * rg + 4 * (ln >> 2) + i;
+        if (col < TAIL && row < D::ROWS) {
+          float sum = 0.f;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) sum += part[((w * RG + rg) * 4 + i) * 64 + ln];
+          const int f = row / E, e = row - f * E;
+          stage[(e * 6 + f) * NP + 16 * NT + col] = sum;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- update and write out, coalesced
+    if (full) {
+      float4* o4 = reinterpret_cast<float4*>(out + tb);
+      float4* r4 = reinterpret_cast<float4*>(res + tb);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < TW4) {
+          const float4 h = reinterpret_cast<const float4*>(stage)[q];
+          if (STAGE) {
+            const float4 u = reinterpret_cast<const float4*>(us)[q];
+            float4 rv;
+            rv.x = ca * rs4[r].x + cdt * h.x;
+            rv.y = ca * rs4[r].y + cdt * h.y;
+            rv.z = ca * rs4[r].z + cdt * h.z;
+            rv.w = ca * rs4[r].w + cdt * h.w;
+            r4[q] = rv;
+            o4[q] = float4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w};
+          } else {
+            o4[q] = h;
+          }
+        }
+      }
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += kThreads) {
+        const float h = stage[q];
+        if (STAGE) {
+          const float rv = ca * res[tb + q] + cdt * h;
+          res[tb + q] = rv;
+          out[tb + q] = us[q] + cb * rv;
+        } else {
+          out[tb + q] = h;
+        }
+      }
+    }
+    __syncthreads();   // the next tile overwrites us, gt, fc and gl
   }
+}
+
+// Resident workgroups for the persistent grid: CUs x workgroups per CU, a multiple of the XCD
+// count (queried once per kernel).
+template <typename Kern>
+int persistent_grid(Kern kern, int ntiles) {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, 0) != hipSuccess || per < 1)
+      per = 1, cus = 256;
+    cached = ((cus * per + kXcds - 1) / kXcds) * kXcds;
+  }
+  const int want = ((ntiles + kXcds - 1) / kXcds) * kXcds;
+  return want < cached ? want : cached;
 }
 
 template <int N>
 hipError_t launch_mfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = MDims<N>::E;
   const int ntiles = (a.K + E - 1) / E;
-  const int nblocks = ((ntiles + kXcds - 1) / kXcds) * kXcds;
   auto* u = static_cast<const float*>(a.u_in);
   auto* o = static_cast<float*>(a.out);
   auto* r = static_cast<float*>(a.res);
   auto* g = static_cast<const float*>(a.geo);
   auto* oc = static_cast<const float*>(ops.opfrag);
-  if (stage)
-    mfma_stage_kernel<N, true><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
-                                                           a.K, ntiles, float(a.a), float(a.b), float(a.dt));
-  else
-    mfma_stage_kernel<N, false><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
-                                                            a.K, ntiles, 0.f, 0.f, 0.f);
+  if (stage) {
+    const int nb = persistent_grid(mfma_stage_kernel<N, true>, ntiles);
+    mfma_stage_kernel<N, true><<<nb, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
+                                                       a.K, ntiles, float(a.a), float(a.b), float(a.dt));
+  } else {
+    const int nb = persistent_grid(mfma_stage_kernel<N, false>, ntiles);
+    mfma_stage_kernel<N, false><<<nb, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
+                                                        a.K, ntiles, 0.f, 0.f, 0.f);
+  }
   return hipGetLastError();
 }
 
