@@ -49,6 +49,29 @@ def bytes_per_elem_stage(N, word):
     return 24 * Np * word + 25 * word + 16
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_0901_1024_amd", "csrc", "kernels.hip")
+
+
+def recorded_traffic(N, prec, K):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
+    this workload, or None when the kernel source has changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"stage_{prec}_n{N}_k{K}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in rec:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(N, n_sample):
     """The FP64 oracle's LSRK4 step timed on the host on a smaller mesh of the same recipe."""
     import numpy as np
@@ -62,10 +85,12 @@ def cpu_baseline(N, n_sample):
     u = dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), *m.x)
     dt = W.stable_dt(m)
     t0 = time.perf_counter()
+    c0 = time.process_time()
     W.lsrk4_step(m, u, dt)
     sec = time.perf_counter() - t0
+    cores = max(1, round((time.process_time() - c0) / sec))
     flops = 5 * m.K * flops_per_elem_stage(N)
-    return {"value": flops / sec / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+    return {"value": flops / sec / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"one LSRK4 step (5 RHS) of the FP64 NumPy oracle on 6*{n_sample}^3 = {m.K} "
                       f"tets, same jitter/permutation/field recipe, N={N}; {sec:.1f} s",
             "seconds": sec}
@@ -80,7 +105,9 @@ def main():
     ap.add_argument("--n", type=int, default=40)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=20)
+    ap.add_argument("--cpu-sample-n", type=int, default=26)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (scales FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -90,6 +117,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 256 * 1024 * 1024 // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}), flush=True)
+        return
 
     import dginputs
     import paper_0901_1024_amd as P
@@ -146,8 +183,9 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": round(tflops_k, 2), "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": round(tflops_k / PEAKS_TFLOPS[prec], 4)}
-    roof["traffic"] = None
-    roof["kernel"] = f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>"
+    roof["traffic"] = recorded_traffic(N, prec, K)
+    roof["kernel"] = (f"mfma_stage_kernel<{N},true>" if prec == "f32" and N in (3, 4)
+                      else f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>")
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     roof["tflops_algorithmic"] = round(tflops_k, 2)

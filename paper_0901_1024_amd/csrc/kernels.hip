@@ -290,16 +290,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
     __syncthreads();
 
-    // ---- issue the loads the rest of this tile and the next tile will need
     float4 rs4[CPT];
-    if (STAGE && full) {
-#pragma unroll
-      for (int r = 0; r < CPT; ++r) {
-        const int q = tid + r * kThreads;
-        if (q < TW4) rs4[r] = reinterpret_cast<const float4*>(res + tb)[q];
-      }
-    }
-    if (tile + nwg < tend) prefetch(tile + nwg);
 
     // ---- face fluxes: fetch every neighbour trace first, then compute
     {
@@ -356,6 +347,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
     }
     __syncthreads();
+    if (STAGE && full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < TW4) rs4[r] = reinterpret_cast<const float4*>(res + tb)[q];
+      }
+    }
+    if (tile + nwg < tend) prefetch(tile + nwg);
 
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li)
     floatx4 acc[TPW];
