@@ -164,28 +164,21 @@ int upload(dg_handle* h, hipStream_t s) {
   ops.insert(ops.end(), R.LIFT.begin(), R.LIFT.end());
   std::vector<char> geo_b = to_prec(geo, h->f64()), ops_b = to_prec(ops, h->f64());
   if (h->lay.opcat_bytes) {
-    // OpCat = [Dr | Ds | Dt | LIFT], each D block padded to roundup(Np, 4) columns, laid out in
-    // the lane order of the contraction kernel (see dgk::OpsView::opfrag)
-    const int Np = h->Np, npp = (Np + 3) / 4 * 4, KD = 3 * npp + 4 * h->Nfp, KS = KD / 4;
-    const int NT = Np / 16;
-    auto opcat = [&](int n, int k) -> double {
-      if (n >= Np) return 0.0;
-      if (k < 3 * npp) {
-        const int mu = k / npp, j = k % npp;
-        if (j >= Np) return 0.0;
-        const std::vector<double>& Dm = mu == 0 ? R.Dr : mu == 1 ? R.Ds : R.Dt;
-        return Dm[size_t(n) * Np + j];
-      }
-      return R.LIFT[size_t(n) * 4 * h->Nfp + (k - 3 * npp)];
-    };
+    // OpCat = [Dr | Ds | Dt | LIFT] in the lane order of the contraction kernel
+    const int Np = h->Np, Nf4 = 4 * h->Nfp;
     std::vector<double> oc(size_t(opfrag_words_for(h->N, h->ts)), 0.0);
-    size_t w = 0;
-    for (int nt = 0; nt < NT; ++nt)
-      for (int kk = 0; kk < KS; ++kk)
-        for (int lane = 0; lane < 64; ++lane) oc[w++] = opcat(16 * nt + lane % 16, 4 * kk + lane / 16);
-    for (int k = 0; k < KD; ++k)
-      for (int c = 0; c < 4; ++c) oc[w++] = opcat(16 * NT + c, k);
-    if (w != oc.size()) return fail(DG_E_ARG, "internal: operator fragment size mismatch");
+    for (size_t w = 0; w < oc.size(); ++w) {
+      int n = -1, blk = -1, col = -1;
+      dgk::opfrag_source(h->N, int(w), &n, &blk, &col);
+      if (n < 0 || blk < 0 || blk > 3 || col < 0) return fail(DG_E_ARG, "internal: bad operator fragment map");
+      if (n >= Np) continue;
+      if (blk < 3 && col < Np) {
+        const std::vector<double>& Dm = blk == 0 ? R.Dr : blk == 1 ? R.Ds : R.Dt;
+        oc[w] = Dm[size_t(n) * Np + col];
+      } else if (blk == 3 && col < Nf4) {
+        oc[w] = R.LIFT[size_t(n) * Nf4 + col];
+      }
+    }
     std::vector<char> oc_b = to_prec(oc, h->f64());
     HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_opcat), oc_b.data(), oc_b.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));

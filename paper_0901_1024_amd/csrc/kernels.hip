@@ -159,11 +159,17 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
 // an (Np x KD) operator times a (KD x 6E) operand, for a tile of E elements.
 //
 // Orientation: rows = (field, element) pairs, columns = nodes, so each result row lands on
-// consecutive nodes. Full 16-node column tiles run on v_mfma_f32_16x16x4f32 with the
-// operator fragments held in VGPRs; the remaining Np mod 16 columns run on
-// v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns). The volume part of the operand is
-// formed on the fly from the field tile in LDS (two LDS reads and two FMAs per value); only
-// the face-flux part is materialised, which keeps LDS near 40 KB and four workgroups per CU.
+// consecutive nodes. Full 16-node column tiles run on v_mfma_f32_16x16x4f32, the remaining
+// Np mod 16 columns on v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns). The volume part
+// of the operand is formed on the fly from a padded copy of the field tile in LDS; the face
+// part (Fscale/2 * flux) is materialised in LDS. Every operand and operator read is a 16-byte
+// LDS read that feeds four k-steps, so the contraction issues few LDS instructions and waits.
+//
+// k-steps of the 16x16x4 contraction (lane group g = lane / 16 holds k-index g of each step):
+//   volume quads  (jb, mu), jb < NPP / 16:  4 steps, group g at column 16 jb + 4 g + s of D_mu;
+//   face quads    fb < NF / 16:             4 steps, group g at face column 16 fb + 4 g + s;
+//   volume singles (r, mu), r < VR:         1 step,  group g at column 16 VB + 4 r + g of D_mu.
+// A quad's four fragments sit in one float4 per lane; singles are one float per lane.
 
 template <int N>
 struct MDims {
@@ -174,19 +180,28 @@ struct MDims {
   static constexpr int TW4 = TW / 4;                 // float4 chunks in a tile
   static constexpr int CPT = (TW4 + kThreads - 1) / kThreads;   // float4 chunks per thread
   static constexpr int NPP = (Np + 3) / 4 * 4;       // volume block per direction, padded
+  static constexpr int ES = 6 * NPP + 4;             // element stride of the padded copy (= 4 mod 8)
+  static constexpr int NF = (Nf4 + 15) / 16 * 16;    // face block, padded
+  static constexpr int RSL = NF + 4;                 // flux row stride (= 4 mod 8)
   static constexpr int KV = 3 * NPP;                 // volume part of the contraction
-  static constexpr int KD = KV + Nf4;                // contraction length (multiple of 4)
-  static constexpr int KS = KD / 4;                  // k-steps; lane group g takes k = 4 kk + g
-  static constexpr int RSL = Nf4 + 2;                // flux row stride, = 2 mod 4 (no bank conflicts)
+  static constexpr int KD = KV + NF;                 // contraction length
+  static constexpr int KS = KD / 4;                  // k-steps
+  static constexpr int VB = NPP / 16;                // full 16-column volume blocks
+  static constexpr int VR = (NPP - 16 * VB) / 4;     // single steps per direction
+  static constexpr int QV = 3 * VB, QF = NF / 16;    // volume and face quads
+  static constexpr int NQ = QV + QF;
   static constexpr int NT = Np / 16;                 // full 16-node column tiles
   static constexpr int TAIL = Np - 16 * NT;          // columns left for the 4x4 blocks
   static constexpr int RT = ROWS / 16;               // 16-row tiles (one field each)
   static constexpr int TILES = RT * NT;              // dealt round-robin to the four waves
   static constexpr int TPW = (TILES + 3) / 4;
   static constexpr int RG = TAIL > 0 ? (ROWS + 63) / 64 : 0;   // 64-row groups of the tail
+  static constexpr int TQ = (KS + 3) / 4;            // tail k-quads per wave (k-quads dealt mod 4)
   static constexpr int FIT = (E * Nf4 + kThreads - 1) / kThreads;  // face nodes per thread
-  // fragment-ordered operator: NT * KS * 64 floats, then the tail columns as [KD][4]
-  static constexpr int OPC = NT * KS * 64 + KD * 4;
+  // fragment-ordered operator: per column tile NQ float4 quads then 3 VR singles per lane,
+  // then the tail columns as [c][KD]
+  static constexpr int OPC = NT * KS * 64 + 4 * KD;
+  static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
   static_assert(NT == 1 || NT == 2 || NT == 4, "a wave's tiles must share one column tile");
   static_assert(RG <= 2 && TAIL <= 4, "tail must fit one 4-column block per row group");
   static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
@@ -203,21 +218,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
     const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
   using D = MDims<N>;
-  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, KV = D::KV,
-                KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT, TAIL = D::TAIL,
-                TILES = D::TILES, TPW = D::TPW, RG = D::RG, FIT = D::FIT, TW = D::TW,
-                TW4 = D::TW4, CPT = D::CPT;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
+                NF = D::NF, KV = D::KV, KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT,
+                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, RG = D::RG, FIT = D::FIT,
+                TW = D::TW, TW4 = D::TW4, CPT = D::CPT, VB = D::VB, VR = D::VR, QV = D::QV,
+                QF = D::QF, NQ = D::NQ, TQ = D::TQ;
   constexpr int G = dgh::kGeoStride;
   constexpr int GW = E * G;                                   // words of geometry per tile
   constexpr int GPT = (GW + kThreads - 1) / kThreads;
   __shared__ __align__(16) float us[TW];              // field tile [e][f][n]
+  __shared__ __align__(16) float up_s[E * ES];        // padded copy [e][f][NPP], zero pad columns
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // Fscale/2 * flux [f E + e][fj]; later staging
+  __shared__ __align__(16) float bfs[NT * KS * 64];   // operator fragments
+  __shared__ __align__(16) float tops[TAIL > 0 ? 4 * KD : 4];   // tail operator, [c][k]
   __shared__ float gt[GW];                            // geometric records of the tile
-  __shared__ float tops[TAIL > 0 ? KD * 4 : 4];       // operator columns of the tail, [k][c]
   __shared__ int32_t fc[E * 4];                       // face records of the tile
   __shared__ uint8_t nbr_s[96 * NFP];                 // neighbour node table
   __shared__ uint8_t fm_s[4 * NFP];                   // face node lists
-  __shared__ float bfs[NT * KS * 64];                 // operator fragments, [nt][kk][lane]
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
@@ -233,22 +250,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   int tile = xcd * TX + wj;
   if (tile >= tend) return;
 
-  // once per workgroup: operator fragments, node tables, tail operator
+  // once per workgroup: operator fragments, node tables, tail operator, zero padding
   const int nt = wave % NT;
   for (int q = tid; q < NT * KS * 64; q += kThreads) bfs[q] = opf[q];
-  const float* bf = bfs + nt * KS * 64 + lane;   // lane's fragment of k-step kk at bf[64 kk]
   for (int q = tid; q < 96 * NFP; q += kThreads) nbr_s[q] = uint8_t(nbrnode[q]);
   for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
   if (TAIL > 0)
-    for (int q = tid; q < KD * 4; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
+    for (int q = tid; q < 4 * KD; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
 
   // prefetch registers: fields, geometry and face records of the next tile
-  float4 pu[CPT];
+  floatx4 pu[CPT];
   float pg[GPT];
   int32_t pf = 0;
-  auto prefetch = [&](int t) {
+  // (inlined so that the prefetch arrays stay in registers)
+  auto prefetch = [&](int t) __attribute__((always_inline)) {
     if (t * E + E <= K) {   // full tiles only; a ragged tile is read directly
-      const float4* s4 = reinterpret_cast<const float4*>(u_in + size_t(t) * E * 6 * NP);
+      const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NP);
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int q = tid + r * kThreads;
@@ -275,7 +292,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int q = tid + r * kThreads;
-        if (q < TW4) reinterpret_cast<float4*>(us)[q] = pu[r];
+        if (q < TW4) reinterpret_cast<floatx4*>(us)[q] = pu[r];
       }
 #pragma unroll
       for (int r = 0; r < GPT; ++r) {
@@ -290,7 +307,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
     __syncthreads();
 
-    float4 rs4[CPT];
+    floatx4 rs4[CPT];
 
     // ---- face fluxes: fetch every neighbour trace first, then compute
     {
@@ -316,6 +333,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             }
           }
         }
+      }
+      // padded copy of the tile for the contraction: rows of NPP, columns >= Np zero
+      for (int q = tid; q < nel * 6 * (NPP / 4); q += kThreads) {
+        const int row = q / (NPP / 4), j4 = 4 * (q - row * (NPP / 4));   // row = 6 e + f
+        const float* src = us + row * NP + j4;
+        floatx4 v;
+        v.x = src[0];
+        v.y = j4 + 1 < NP ? src[1] : 0.f;
+        v.z = j4 + 2 < NP ? src[2] : 0.f;
+        v.w = j4 + 3 < NP ? src[3] : 0.f;
+        *reinterpret_cast<floatx4*>(up_s + (row / 6) * ES + (row % 6) * NPP + j4) = v;
+      }
+      // face columns NF4 .. NF-1 of every row are padding: keep them zero
+      for (int q = tid; q < D::ROWS * (NF - NF4); q += kThreads) {
+        const int row = q / (NF - NF4);
+        gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
       }
 #pragma unroll
       for (int r = 0; r < FIT; ++r) {
@@ -351,12 +384,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int q = tid + r * kThreads;
-        if (q < TW4) rs4[r] = reinterpret_cast<const float4*>(res + tb)[q];
+        if (q < TW4) rs4[r] = reinterpret_cast<const floatx4*>(res + tb)[q];
       }
     }
     if (tile + nwg < tend) prefetch(tile + nwg);
 
-    // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li)
+    // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
+    // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
     floatx4 acc[TPW];
     {
       float pc[TPW][3], qc[TPW][3];   // operand = pc[mu] * V_c[j] + qc[mu] * V_b[j]
@@ -377,40 +411,76 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           pc[t][mu] = sg * cm[3 * mu + b];
           qc[t][mu] = -sg * cm[3 * mu + c];
         }
-        vc[t] = us + li * 6 * NP + (srcf + c) * NP + g4;
-        vb[t] = us + li * 6 * NP + (srcf + b) * NP + g4;
-        fl[t] = gl + (f * E + li) * RSL + g4;
+        vc[t] = up_s + li * ES + (srcf + c) * NPP;
+        vb[t] = up_s + li * ES + (srcf + b) * NPP;
+        fl[t] = gl + (f * E + li) * RSL + 4 * g4;
       }
+      const floatx4* bq = reinterpret_cast<const floatx4*>(bfs + nt * KS * 64) + lane;   // quads
+      const float* bs = bfs + nt * KS * 64 + NQ * 256 + lane;                         // singles
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        // branch-free: a wave with fewer than TPW tiles repeats its last one and drops the result
+      for (int jb = 0; jb < VB; ++jb) {
+        floatx4 xc[TPW], xb[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
-          float av;
-          if (4 * kk < KV) {
-            const int mu = (4 * kk) / NPP, j0 = 4 * kk - mu * NPP;
-            if (j0 + 3 < NP) {
-              av = pc[t][mu] * vc[t][j0] + qc[t][mu] * vb[t][j0];
-            } else {   // last block of a direction: columns j >= Np are zero padding
-              const int jj = min(j0, NP - 1 - g4);
-              const float v = pc[t][mu] * vc[t][jj] + qc[t][mu] * vb[t][jj];
-              av = (j0 + g4 < NP) ? v : 0.f;
+          xc[t] = *reinterpret_cast<const floatx4*>(vc[t] + 16 * jb + 4 * g4);
+          xb[t] = *reinterpret_cast<const floatx4*>(vb[t] + 16 * jb + 4 * g4);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const floatx4 w = bq[64 * (3 * jb + mu)];
+          const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+              const float xcs = s == 0 ? xc[t].x : s == 1 ? xc[t].y : s == 2 ? xc[t].z : xc[t].w;
+              const float xbs = s == 0 ? xb[t].x : s == 1 ? xb[t].y : s == 2 ? xb[t].z : xb[t].w;
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pc[t][mu] * xcs + qc[t][mu] * xbs, wv[s],
+                                                            acc[t], 0, 0, 0);
             }
-          } else {
-            av = fl[t][4 * kk - KV];
+        }
+      }
+#pragma unroll
+      for (int fb = 0; fb < QF; ++fb) {
+        floatx4 xf[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) xf[t] = *reinterpret_cast<const floatx4*>(fl[t] + 16 * fb);
+        const floatx4 w = bq[64 * (QV + fb)];
+        const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) {
+            const float xs = s == 0 ? xf[t].x : s == 1 ? xf[t].y : s == 2 ? xf[t].z : xf[t].w;
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs, wv[s], acc[t], 0, 0, 0);
           }
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[64 * kk], acc[t], 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < VR; ++r) {
+        float xc1[TPW], xb1[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          xc1[t] = vc[t][16 * VB + 4 * r + g4];   // columns >= Np read the zero padding
+          xb1[t] = vb[t][16 * VB + 4 * r + g4];
+        }
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const float w = bs[64 * (3 * r + mu)];
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pc[t][mu] * xc1[t] + qc[t][mu] * xb1[t], w,
+                                                          acc[t], 0, 0, 0);
         }
       }
     }
 
     // ---- tail columns 16 NT .. Np-1 on v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns):
-    // every wave takes the k = wave (mod 4) quarter of both row groups; partial sums meet in LDS
-    floatx4 tacc[RG > 0 ? RG : 1][2];
+    // wave w takes the k-quads kq = w (mod 4) of both row groups; partial sums meet in LDS
+    floatx4 tacc[RG > 0 ? RG : 1];
     if (TAIL > 0) {
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) {
-        tacc[rg][0] = tacc[rg][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        tacc[rg] = floatx4{0.f, 0.f, 0.f, 0.f};
         const int row = 64 * rg + lane;
         const bool rowok = row < D::ROWS;
         const int f = rowok ? row / E : 0, e = row - (row / E) * E;
@@ -424,26 +494,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           pt[mu] = sg * cm[3 * mu + b];
           qt[mu] = -sg * cm[3 * mu + c];
         }
-        const float* tvc = us + e * 6 * NP + (srcf + c) * NP + wave;
-        const float* tvb = us + e * 6 * NP + (srcf + b) * NP + wave;
-        const float* tfl = gl + (rowok ? row : 0) * RSL + wave;
-        const float* top = tops + 4 * wave + (lane & 3);
+        const float* tvc = up_s + e * ES + (srcf + c) * NPP;
+        const float* tvb = up_s + e * ES + (srcf + b) * NPP;
+        const float* tfl = gl + (rowok ? row : 0) * RSL;
+        const float* top = tops + (lane & 3) * KD;
 #pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {   // k = 4 kk + wave
-          float av;
-          if (4 * kk < KV) {
-            const int mu = (4 * kk) / NPP, j0 = 4 * kk - mu * NPP;
-            if (j0 + 3 < NP) {
-              av = pt[mu] * tvc[j0] + qt[mu] * tvb[j0];
+        for (int i = 0; i < TQ; ++i) {
+          const int k0 = 4 * (wave + 4 * i);   // wave-uniform
+          if (k0 < KD) {
+            const floatx4 w = *reinterpret_cast<const floatx4*>(top + k0);
+            floatx4 av;
+            if (k0 < KV) {
+              const int mu = k0 / NPP, j0 = k0 - mu * NPP;
+              const float p = mu == 0 ? pt[0] : mu == 1 ? pt[1] : pt[2];
+              const float qv = mu == 0 ? qt[0] : mu == 1 ? qt[1] : qt[2];
+              const floatx4 xc = *reinterpret_cast<const floatx4*>(tvc + j0);
+              const floatx4 xb = *reinterpret_cast<const floatx4*>(tvb + j0);
+              av = floatx4{p * xc.x + qv * xb.x, p * xc.y + qv * xb.y, p * xc.z + qv * xb.z,
+                          p * xc.w + qv * xb.w};
             } else {
-              const int jj = min(j0, NP - 1 - wave);
-              const float v = pt[mu] * tvc[jj] + qt[mu] * tvb[jj];
-              av = (j0 + wave < NP) ? v : 0.f;
+              av = *reinterpret_cast<const floatx4*>(tfl + (k0 - KV));
+              if (!rowok) av = floatx4{0.f, 0.f, 0.f, 0.f};
             }
-          } else {
-            av = rowok ? tfl[4 * kk - KV] : 0.f;
+            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.x, w.x, tacc[rg], 0, 0, 0);
+            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.y, w.y, tacc[rg], 0, 0, 0);
+            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.z, w.z, tacc[rg], 0, 0, 0);
+            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.w, w.w, tacc[rg], 0, 0, 0);
           }
-          tacc[rg][kk & 1] = __builtin_amdgcn_mfma_f32_4x4x1f32(av, top[16 * kk], tacc[rg][kk & 1], 0, 0, 0);
         }
       }
     }
@@ -465,7 +542,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) part[((wave * RG + rg) * 4 + i) * 64 + lane] = tacc[rg][0][i] + tacc[rg][1][i];
+        for (int i = 0; i < 4; ++i) part[((wave * RG + rg) * 4 + i) * 64 + lane] = tacc[rg][i];
       __syncthreads();
       // lane (block, column) of row group rg holds rows 64 rg + 4 block + i, node 16 NT + column
       for (int q = tid; q < RG * 4 * 64; q += kThreads) {
@@ -484,22 +561,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     // ---- update and write out, coalesced
     if (full) {
-      float4* o4 = reinterpret_cast<float4*>(out + tb);
-      float4* r4 = reinterpret_cast<float4*>(res + tb);
+      floatx4* o4 = reinterpret_cast<floatx4*>(out + tb);
+      floatx4* r4 = reinterpret_cast<floatx4*>(res + tb);
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int q = tid + r * kThreads;
         if (q < TW4) {
-          const float4 h = reinterpret_cast<const float4*>(stage)[q];
+          const floatx4 h = reinterpret_cast<const floatx4*>(stage)[q];
           if (STAGE) {
-            const float4 u = reinterpret_cast<const float4*>(us)[q];
-            float4 rv;
+            const floatx4 u = reinterpret_cast<const floatx4*>(us)[q];
+            floatx4 rv;
             rv.x = ca * rs4[r].x + cdt * h.x;
             rv.y = ca * rs4[r].y + cdt * h.y;
             rv.z = ca * rs4[r].z + cdt * h.z;
             rv.w = ca * rs4[r].w + cdt * h.w;
             r4[q] = rv;
-            o4[q] = float4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w};
+            o4[q] = floatx4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w};
           } else {
             o4[q] = h;
           }
@@ -691,6 +768,60 @@ int opcat_words(int N) {
 }
 
 bool mfma_order(int N) { return N == 3 || N == 4; }
+
+namespace {
+// Decodes a column k of the padded concatenation [D_r | D_s | D_t] (NPP columns each) + LIFT
+// (NF columns) into operator block and column within it.
+template <int N>
+void opcat_column(int k, int* blk, int* col) {
+  using D = MDims<N>;
+  if (k < D::KV) {
+    *blk = k / D::NPP;
+    *col = k % D::NPP;
+  } else {
+    *blk = 3;
+    *col = k - D::KV;
+  }
+}
+
+template <int N>
+void opfrag_source_t(int w, int* n, int* blk, int* col) {
+  using D = MDims<N>;
+  const int per_tile = D::KS * 64;
+  int k = 0;
+  if (w < D::NT * per_tile) {
+    const int nt = w / per_tile, r = w - nt * per_tile;
+    if (r < D::NQ * 256) {   // quad q, lane, step s
+      const int q = r / 256, lane = (r / 4) % 64, s = r % 4, g = lane / 16;
+      *n = 16 * nt + lane % 16;
+      if (q < D::QV) {
+        const int jb = q / 3, mu = q % 3;
+        k = mu * D::NPP + 16 * jb + 4 * g + s;
+      } else {
+        k = D::KV + 16 * (q - D::QV) + 4 * g + s;
+      }
+    } else {                 // single (r, mu), lane
+      const int r1 = r - D::NQ * 256, sg = r1 / 64, lane = r1 % 64, g = lane / 16;
+      const int rr = sg / 3, mu = sg % 3;
+      *n = 16 * nt + lane % 16;
+      k = mu * D::NPP + 16 * D::VB + 4 * rr + g;
+    }
+  } else {                   // tail [c][k]
+    const int r = w - D::NT * per_tile;
+    *n = 16 * D::NT + r / D::KD;
+    k = r % D::KD;
+  }
+  opcat_column<N>(k, blk, col);
+}
+}  // namespace
+
+void opfrag_source(int N, int w, int* n, int* blk, int* col) {
+  switch (N) {
+    case 3: return opfrag_source_t<3>(w, n, blk, col);
+    case 4: return opfrag_source_t<4>(w, n, blk, col);
+  }
+  *n = *blk = *col = -1;
+}
 
 int tile_elems(int N) {
   switch (N) {

@@ -16,11 +16,9 @@ struct OpsView {
   const void* M;
   const int32_t* fmask;    // 4 x Nfp
   const int32_t* nbrnode;  // 4 x 4 x 6 x Nfp
-  // The concatenated operator OpCat = [Dr | Ds | Dt | LIFT] (Np x KD, each D block
-  // zero-padded to roundup(Np, 4) columns, KD = 3 roundup(Np, 4) + 4 Nfp) in MFMA fragment
-  // order (FP32 contraction kernels only; NULL where unused):
-  //   [nt][kk][lane] = OpCat[16 nt + lane % 16][4 kk + lane / 16]  for the full 16-node tiles,
-  //   then [k][c]    = OpCat[16 NT + c][k] (zero for rows >= Np)    for the remaining nodes.
+  // The concatenated operator OpCat = [Dr | Ds | Dt | LIFT] (each D block zero-padded to
+  // roundup(Np, 4) columns, LIFT to roundup(4 Nfp, 16)) in the fragment order of the FP32
+  // contraction kernel (NULL where unused); opfrag_source() says which entry each word holds.
   const void* opfrag;
 };
 
@@ -28,6 +26,10 @@ struct OpsView {
 int opcat_words(int N);
 // Whether the FP32 MFMA stage kernel serves order N.
 bool mfma_order(int N);
+// Word w of the fragment-ordered operator of order N holds row n of operator block blk
+// (0, 1, 2 = Dr, Ds, Dt; 3 = LIFT) at column col; it is zero when n, col fall outside the
+// operator (n >= Np, col >= Np for a D block, col >= 4 Nfp for LIFT).
+void opfrag_source(int N, int w, int* n, int* blk, int* col);
 
 struct StageArgs {
   const void* u_in;  // internal layout [K][6][Np]
