@@ -14,6 +14,8 @@
 // result on chip, so each field value crosses HBM once per stage.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "host/meshbuild.hpp"
 #include "kernels.hpp"
 
@@ -262,21 +264,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   floatx4 pu[CPT];
   float pg[GPT];
   int32_t pf = 0;
-  // (inlined so that the prefetch arrays stay in registers)
+  // Inlined so that the prefetch arrays stay in registers. Every thread loads every slot
+  // (indices clamped into the tile): exec-masked loads make the compiler wait for all
+  // outstanding loads before reusing their registers.
   auto prefetch = [&](int t) __attribute__((always_inline)) {
     if (t * E + E <= K) {   // full tiles only; a ragged tile is read directly
       const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NP);
 #pragma unroll
-      for (int r = 0; r < CPT; ++r) {
-        const int q = tid + r * kThreads;
-        if (q < TW4) pu[r] = s4[q];
-      }
+      for (int r = 0; r < CPT; ++r) pu[r] = s4[min(tid + r * kThreads, TW4 - 1)];
 #pragma unroll
-      for (int r = 0; r < GPT; ++r) {
-        const int q = tid + r * kThreads;
-        if (q < GW) pg[r] = geo[size_t(t) * GW + q];
-      }
-      if (tid < E * 4) pf = fcode[size_t(t) * E * 4 + tid];
+      for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * kThreads, GW - 1)];
+      pf = fcode[size_t(t) * E * 4 + min(tid, E * 4 - 1)];
     }
   };
   prefetch(tile);
@@ -382,10 +380,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     __syncthreads();
     if (STAGE && full) {
 #pragma unroll
-      for (int r = 0; r < CPT; ++r) {
-        const int q = tid + r * kThreads;
-        if (q < TW4) rs4[r] = reinterpret_cast<const floatx4*>(res + tb)[q];
-      }
+      for (int r = 0; r < CPT; ++r)   // clamped like the prefetch
+        rs4[r] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + r * kThreads, TW4 - 1)];
     }
     if (tile + nwg < tend) prefetch(tile + nwg);
 
@@ -475,46 +471,51 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
 
     // ---- tail columns 16 NT .. Np-1 on v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns):
-    // wave w takes the k-quads kq = w (mod 4) of both row groups; partial sums meet in LDS
+    // wave w takes the k-quads kq = w (mod 4) of both row groups; partial sums meet in LDS.
+    // The loop is instantiated per wave so that every k-quad's direction and column are
+    // compile-time constants (straight-line code the compiler can pipeline).
     floatx4 tacc[RG > 0 ? RG : 1];
     if (TAIL > 0) {
+      float pt[RG][3], qt[RG][3];
+      bool rowok[RG];
+      int oc[RG], ob[RG], of[RG];
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) {
         tacc[rg] = floatx4{0.f, 0.f, 0.f, 0.f};
         const int row = 64 * rg + lane;
-        const bool rowok = row < D::ROWS;
-        const int f = rowok ? row / E : 0, e = row - (row / E) * E;
+        rowok[rg] = row < D::ROWS;
+        const int f = rowok[rg] ? row / E : 0, e = row - (row / E) * E;
         const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
         const int srcf = f < 3 ? 3 : 0;
-        const float sg = rowok ? (f < 3 ? 1.f : -1.f) : 0.f;
+        const float sg = rowok[rg] ? (f < 3 ? 1.f : -1.f) : 0.f;
         const float* cm = gt + e * G;
-        float pt[3], qt[3];
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu) {
-          pt[mu] = sg * cm[3 * mu + b];
-          qt[mu] = -sg * cm[3 * mu + c];
+          pt[rg][mu] = sg * cm[3 * mu + b];
+          qt[rg][mu] = -sg * cm[3 * mu + c];
         }
-        const float* tvc = up_s + e * ES + (srcf + c) * NPP;
-        const float* tvb = up_s + e * ES + (srcf + b) * NPP;
-        const float* tfl = gl + (rowok ? row : 0) * RSL;
-        const float* top = tops + (lane & 3) * KD;
+        oc[rg] = e * ES + (srcf + c) * NPP;   // up_s offsets of V_c, V_b
+        ob[rg] = e * ES + (srcf + b) * NPP;
+        of[rg] = (rowok[rg] ? row : 0) * RSL; // gl offset of the flux row
+      }
+      const float* top = tops + (lane & 3) * KD;
+      auto tail = [&](auto wc) __attribute__((always_inline)) {
+        constexpr int W = decltype(wc)::value;
 #pragma unroll
-        for (int i = 0; i < TQ; ++i) {
-          const int k0 = 4 * (wave + 4 * i);   // wave-uniform
-          if (k0 < KD) {
-            const floatx4 w = *reinterpret_cast<const floatx4*>(top + k0);
+        for (int i = 0; 4 * (W + 4 * i) < KD; ++i) {
+          const int k0 = 4 * (W + 4 * i);
+          const floatx4 w = *reinterpret_cast<const floatx4*>(top + k0);
+#pragma unroll
+          for (int rg = 0; rg < RG; ++rg) {
             floatx4 av;
             if (k0 < KV) {
               const int mu = k0 / NPP, j0 = k0 - mu * NPP;
-              const float p = mu == 0 ? pt[0] : mu == 1 ? pt[1] : pt[2];
-              const float qv = mu == 0 ? qt[0] : mu == 1 ? qt[1] : qt[2];
-              const floatx4 xc = *reinterpret_cast<const floatx4*>(tvc + j0);
-              const floatx4 xb = *reinterpret_cast<const floatx4*>(tvb + j0);
-              av = floatx4{p * xc.x + qv * xb.x, p * xc.y + qv * xb.y, p * xc.z + qv * xb.z,
-                          p * xc.w + qv * xb.w};
+              const floatx4 xc = *reinterpret_cast<const floatx4*>(up_s + oc[rg] + j0);
+              const floatx4 xb = *reinterpret_cast<const floatx4*>(up_s + ob[rg] + j0);
+              av = pt[rg][mu] * xc + qt[rg][mu] * xb;
             } else {
-              av = *reinterpret_cast<const floatx4*>(tfl + (k0 - KV));
-              if (!rowok) av = floatx4{0.f, 0.f, 0.f, 0.f};
+              av = *reinterpret_cast<const floatx4*>(gl + of[rg] + (k0 - KV));
+              if (!rowok[rg]) av = floatx4{0.f, 0.f, 0.f, 0.f};
             }
             tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.x, w.x, tacc[rg], 0, 0, 0);
             tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.y, w.y, tacc[rg], 0, 0, 0);
@@ -522,6 +523,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.w, w.w, tacc[rg], 0, 0, 0);
           }
         }
+      };
+      switch (wave) {
+        case 0: tail(std::integral_constant<int, 0>{}); break;
+        case 1: tail(std::integral_constant<int, 1>{}); break;
+        case 2: tail(std::integral_constant<int, 2>{}); break;
+        default: tail(std::integral_constant<int, 3>{}); break;
       }
     }
     __syncthreads();   // flux rows are read: reuse them for the staging
