@@ -14,8 +14,6 @@
 // result on chip, so each field value crosses HBM once per stage.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "host/meshbuild.hpp"
 #include "kernels.hpp"
 
@@ -161,11 +159,14 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
 // an (Np x KD) operator times a (KD x 6E) operand, for a tile of E elements.
 //
 // Orientation: rows = (field, element) pairs, columns = nodes, so each result row lands on
-// consecutive nodes. Full 16-node column tiles run on v_mfma_f32_16x16x4f32, the remaining
-// Np mod 16 columns on v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns). The volume part
-// of the operand is formed on the fly from a padded copy of the field tile in LDS; the face
-// part (Fscale/2 * flux) is materialised in LDS. Every operand and operator read is a 16-byte
-// LDS read that feeds four k-steps, so the contraction issues few LDS instructions and waits.
+// consecutive nodes. Full 16-node column tiles run on v_mfma_f32_16x16x4f32. The remaining
+// Np mod 16 columns ride along on v_mfma_f32_4x4x1f32 fed with the same operand registers:
+// its 16 blocks are read as (k-group g, row quad) pairs, so lane (row, g) supplies the value
+// it already holds for the 16x16x4 step, the tail operator supplies column c of k-group g,
+// and a sum over the four k-groups (cross-lane) finishes the tail. The volume part of the
+// operand is formed on the fly from a padded copy of the field tile in LDS; the face part
+// (Fscale/2 * flux) is materialised in LDS. Every operand and operator read is a 16-byte LDS
+// read that feeds four k-steps, so the contraction issues few LDS instructions and waits.
 //
 // k-steps of the 16x16x4 contraction (lane group g = lane / 16 holds k-index g of each step):
 //   volume quads  (jb, mu), jb < NPP / 16:  4 steps, group g at column 16 jb + 4 g + s of D_mu;
@@ -197,18 +198,16 @@ struct MDims {
   static constexpr int RT = ROWS / 16;               // 16-row tiles (one field each)
   static constexpr int TILES = RT * NT;              // dealt round-robin to the four waves
   static constexpr int TPW = (TILES + 3) / 4;
-  static constexpr int RG = TAIL > 0 ? (ROWS + 63) / 64 : 0;   // 64-row groups of the tail
-  static constexpr int TQ = (KS + 3) / 4;            // tail k-quads per wave (k-quads dealt mod 4)
   static constexpr int FIT = (E * Nf4 + kThreads - 1) / kThreads;  // face nodes per thread
-  // fragment-ordered operator: per column tile NQ float4 quads then 3 VR singles per lane,
-  // then the tail columns as [c][KD]
-  static constexpr int OPC = NT * KS * 64 + 4 * KD;
+  // fragment-ordered operator: per column tile NQ float4 quads then 3 VR singles per lane;
+  // then the tail columns, per quad [g][c][4 steps], per single [g][c]
+  static constexpr int OPC = NT * KS * 64 + KS * 16;
   static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
   static_assert(NT == 1 || NT == 2 || NT == 4, "a wave's tiles must share one column tile");
-  static_assert(RG <= 2 && TAIL <= 4, "tail must fit one 4-column block per row group");
+  static_assert(TAIL <= 4, "the tail is one 4-column block");
   static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
-  // after the contraction the flux rows are free: rhs staging [e][f][n] and tail partials
-  static_assert(TW + 4 * RG * 256 <= ROWS * RSL, "staging must fit in the flux rows");
+  // after the contraction the flux rows are free for the rhs staging [e][f][n]
+  static_assert(TW <= ROWS * RSL, "staging must fit in the flux rows");
 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -222,9 +221,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   using D = MDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
                 NF = D::NF, KV = D::KV, KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT,
-                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, RG = D::RG, FIT = D::FIT,
-                TW = D::TW, TW4 = D::TW4, CPT = D::CPT, VB = D::VB, VR = D::VR, QV = D::QV,
-                QF = D::QF, NQ = D::NQ, TQ = D::TQ;
+                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, FIT = D::FIT, TW = D::TW,
+                TW4 = D::TW4, CPT = D::CPT, VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF,
+                NQ = D::NQ;
   constexpr int G = dgh::kGeoStride;
   constexpr int GW = E * G;                                   // words of geometry per tile
   constexpr int GPT = (GW + kThreads - 1) / kThreads;
@@ -232,7 +231,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   __shared__ __align__(16) float up_s[E * ES];        // padded copy [e][f][NPP], zero pad columns
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // Fscale/2 * flux [f E + e][fj]; later staging
   __shared__ __align__(16) float bfs[NT * KS * 64];   // operator fragments
-  __shared__ __align__(16) float tops[TAIL > 0 ? 4 * KD : 4];   // tail operator, [c][k]
+  __shared__ __align__(16) float tops[TAIL > 0 ? KS * 16 : 4];  // tail operator fragments
   __shared__ float gt[GW];                            // geometric records of the tile
   __shared__ int32_t fc[E * 4];                       // face records of the tile
   __shared__ uint8_t nbr_s[96 * NFP];                 // neighbour node table
@@ -258,7 +257,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int q = tid; q < 96 * NFP; q += kThreads) nbr_s[q] = uint8_t(nbrnode[q]);
   for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
   if (TAIL > 0)
-    for (int q = tid; q < 4 * KD; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
+    for (int q = tid; q < KS * 16; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
 
   // prefetch registers: fields, geometry and face records of the next tile
   floatx4 pu[CPT];
@@ -387,7 +386,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
     // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
-    floatx4 acc[TPW];
+    // The tail columns accumulate in tacc (kept by the waves of column tile 0).
+    floatx4 acc[TPW], tacc[TPW];
     {
       float pc[TPW][3], qc[TPW][3];   // operand = pc[mu] * V_c[j] + qc[mu] * V_b[j]
       const float* vc[TPW];
@@ -396,6 +396,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        tacc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         const int tt = min(wave + 4 * t, TILES - 1);
         const int f = tt / NT;
         const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
@@ -413,6 +414,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
       const floatx4* bq = reinterpret_cast<const floatx4*>(bfs + nt * KS * 64) + lane;   // quads
       const float* bs = bfs + nt * KS * 64 + NQ * 256 + lane;                         // singles
+      const int tl = 4 * g4 + (li & 3);   // tail fragment slot: k-group g4, column li mod 4
+      const floatx4* tq = reinterpret_cast<const floatx4*>(tops) + tl;
+      const float* ts = tops + NQ * 64 + tl;
 #pragma unroll
       for (int jb = 0; jb < VB; ++jb) {
         floatx4 xc[TPW], xb[TPW];
@@ -425,15 +429,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int mu = 0; mu < 3; ++mu) {
           const floatx4 w = bq[64 * (3 * jb + mu)];
           const float wv[4] = {w.x, w.y, w.z, w.w};
+          floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+          if (TAIL > 0) z = tq[16 * (3 * jb + mu)];
+          const float zv[4] = {z.x, z.y, z.z, z.w};
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
+          for (int s = 0; s < 4; ++s) {
+            float av[TPW];
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
               const float xcs = s == 0 ? xc[t].x : s == 1 ? xc[t].y : s == 2 ? xc[t].z : xc[t].w;
               const float xbs = s == 0 ? xb[t].x : s == 1 ? xb[t].y : s == 2 ? xb[t].z : xb[t].w;
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pc[t][mu] * xcs + qc[t][mu] * xbs, wv[s],
-                                                            acc[t], 0, 0, 0);
+              av[t] = pc[t][mu] * xcs + qc[t][mu] * xbs;
             }
+            // the 16x16x4 products of all tiles first, then the short tail products
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], wv[s], acc[t], 0, 0, 0);
+            if (TAIL > 0)
+#pragma unroll
+              for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[t], zv[s], tacc[t], 0, 0, 0);
+          }
         }
       }
 #pragma unroll
@@ -443,13 +457,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int t = 0; t < TPW; ++t) xf[t] = *reinterpret_cast<const floatx4*>(fl[t] + 16 * fb);
         const floatx4 w = bq[64 * (QV + fb)];
         const float wv[4] = {w.x, w.y, w.z, w.w};
+        floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (TAIL > 0) z = tq[16 * (QV + fb)];
+        const float zv[4] = {z.x, z.y, z.z, z.w};
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s) {
+          float xs[TPW];
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) {
-            const float xs = s == 0 ? xf[t].x : s == 1 ? xf[t].y : s == 2 ? xf[t].z : xf[t].w;
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs, wv[s], acc[t], 0, 0, 0);
-          }
+          for (int t = 0; t < TPW; ++t) xs[t] = s == 0 ? xf[t].x : s == 1 ? xf[t].y : s == 2 ? xf[t].z : xf[t].w;
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[t], wv[s], acc[t], 0, 0, 0);
+          if (TAIL > 0)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(xs[t], zv[s], tacc[t], 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int r = 0; r < VR; ++r) {
@@ -462,78 +483,36 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu) {
           const float w = bs[64 * (3 * r + mu)];
+          const float zs = TAIL > 0 ? ts[16 * (3 * r + mu)] : 0.f;
+          float av[TPW];
 #pragma unroll
-          for (int t = 0; t < TPW; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pc[t][mu] * xc1[t] + qc[t][mu] * xb1[t], w,
-                                                          acc[t], 0, 0, 0);
+          for (int t = 0; t < TPW; ++t) av[t] = pc[t][mu] * xc1[t] + qc[t][mu] * xb1[t];
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], w, acc[t], 0, 0, 0);
+          if (TAIL > 0)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[t], zs, tacc[t], 0, 0, 0);
         }
       }
     }
 
-    // ---- tail columns 16 NT .. Np-1 on v_mfma_f32_4x4x1f32 (16 blocks = 64 rows x 4 columns):
-    // wave w takes the k-quads kq = w (mod 4) of both row groups; partial sums meet in LDS.
-    // The loop is instantiated per wave so that every k-quad's direction and column are
-    // compile-time constants (straight-line code the compiler can pipeline).
-    floatx4 tacc[RG > 0 ? RG : 1];
+    // tail: sum the partial results of the four k-groups (lanes li, li + 16, li + 32, li + 48)
     if (TAIL > 0) {
-      float pt[RG][3], qt[RG][3];
-      bool rowok[RG];
-      int oc[RG], ob[RG], of[RG];
 #pragma unroll
-      for (int rg = 0; rg < RG; ++rg) {
-        tacc[rg] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const int row = 64 * rg + lane;
-        rowok[rg] = row < D::ROWS;
-        const int f = rowok[rg] ? row / E : 0, e = row - (row / E) * E;
-        const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
-        const int srcf = f < 3 ? 3 : 0;
-        const float sg = rowok[rg] ? (f < 3 ? 1.f : -1.f) : 0.f;
-        const float* cm = gt + e * G;
+      for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int mu = 0; mu < 3; ++mu) {
-          pt[rg][mu] = sg * cm[3 * mu + b];
-          qt[rg][mu] = -sg * cm[3 * mu + c];
+        for (int i = 0; i < 4; ++i) {
+          float v = tacc[t][i];
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          tacc[t][i] = v;
         }
-        oc[rg] = e * ES + (srcf + c) * NPP;   // up_s offsets of V_c, V_b
-        ob[rg] = e * ES + (srcf + b) * NPP;
-        of[rg] = (rowok[rg] ? row : 0) * RSL; // gl offset of the flux row
-      }
-      const float* top = tops + (lane & 3) * KD;
-      auto tail = [&](auto wc) __attribute__((always_inline)) {
-        constexpr int W = decltype(wc)::value;
-#pragma unroll
-        for (int i = 0; 4 * (W + 4 * i) < KD; ++i) {
-          const int k0 = 4 * (W + 4 * i);
-          const floatx4 w = *reinterpret_cast<const floatx4*>(top + k0);
-#pragma unroll
-          for (int rg = 0; rg < RG; ++rg) {
-            floatx4 av;
-            if (k0 < KV) {
-              const int mu = k0 / NPP, j0 = k0 - mu * NPP;
-              const floatx4 xc = *reinterpret_cast<const floatx4*>(up_s + oc[rg] + j0);
-              const floatx4 xb = *reinterpret_cast<const floatx4*>(up_s + ob[rg] + j0);
-              av = pt[rg][mu] * xc + qt[rg][mu] * xb;
-            } else {
-              av = *reinterpret_cast<const floatx4*>(gl + of[rg] + (k0 - KV));
-              if (!rowok[rg]) av = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
-            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.x, w.x, tacc[rg], 0, 0, 0);
-            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.y, w.y, tacc[rg], 0, 0, 0);
-            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.z, w.z, tacc[rg], 0, 0, 0);
-            tacc[rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av.w, w.w, tacc[rg], 0, 0, 0);
-          }
-        }
-      };
-      switch (wave) {
-        case 0: tail(std::integral_constant<int, 0>{}); break;
-        case 1: tail(std::integral_constant<int, 1>{}); break;
-        case 2: tail(std::integral_constant<int, 2>{}); break;
-        default: tail(std::integral_constant<int, 3>{}); break;
-      }
     }
     __syncthreads();   // flux rows are read: reuse them for the staging
 
-    // ---- stage the right-hand side [e][f][n] in LDS
+    // ---- stage the right-hand side [e][f][n] in LDS. 16x16x4 result: lane (li, g4), register
+    // i = row 4 g4 + i, node 16 nt + li. Tail (column tile 0 waves, lanes g4 = 0): lane li,
+    // register i = row 4 (li / 4) + i, node 16 NT + li mod 4.
     float* stage = gl;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
@@ -542,25 +521,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         const int f = tt / NT;
 #pragma unroll
         for (int i = 0; i < 4; ++i) stage[((4 * g4 + i) * 6 + f) * NP + 16 * nt + li] = acc[t][i];
-      }
-    }
-    if (TAIL > 0) {
-      float* part = gl + TW;   // [wave][rg][i][lane]
+        if (TAIL > 0 && nt == 0 && g4 == 0 && (li & 3) < TAIL) {
 #pragma unroll
-      for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part[((wave * RG + rg) * 4 + i) * 64 + lane] = tacc[rg][i];
-      __syncthreads();
-      // lane (block, column) of row group rg holds rows 64 rg + 4 block + i, node 16 NT + column
-      for (int q = tid; q < RG * 4 * 64; q += kThreads) {
-        const int rg = q / 256, i = (q / 64) % 4, ln = q % 64;
-        const int col = ln & 3, row = 64 * rg + 4 * (ln >> 2) + i;
-        if (col < TAIL && row < D::ROWS) {
-          float sum = 0.f;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) sum += part[((w * RG + rg) * 4 + i) * 64 + ln];
-          const int f = row / E, e = row - f * E;
-          stage[(e * 6 + f) * NP + 16 * NT + col] = sum;
+          for (int i = 0; i < 4; ++i)
+            stage[((4 * (li >> 2) + i) * 6 + f) * NP + 16 * NT + (li & 3)] = tacc[t][i];
         }
       }
     }
@@ -813,10 +777,17 @@ void opfrag_source_t(int w, int* n, int* blk, int* col) {
       *n = 16 * nt + lane % 16;
       k = mu * D::NPP + 16 * D::VB + 4 * rr + g;
     }
-  } else {                   // tail [c][k]
+  } else {                   // tail: quads [q][g][c][s], then singles [(r, mu)][g][c]
     const int r = w - D::NT * per_tile;
-    *n = 16 * D::NT + r / D::KD;
-    k = r % D::KD;
+    if (r < D::NQ * 64) {
+      const int q = r / 64, g = (r / 16) % 4, c = (r / 4) % 4, s = r % 4;
+      *n = 16 * D::NT + c;
+      k = q < D::QV ? (q % 3) * D::NPP + 16 * (q / 3) + 4 * g + s : D::KV + 16 * (q - D::QV) + 4 * g + s;
+    } else {
+      const int r1 = r - D::NQ * 64, sg = r1 / 16, g = (r1 / 4) % 4, c = r1 % 4;
+      *n = 16 * D::NT + c;
+      k = (sg % 3) * D::NPP + 16 * D::VB + 4 * (sg / 3) + g;
+    }
   }
   opcat_column<N>(k, blk, col);
 }
