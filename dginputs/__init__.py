@@ -23,6 +23,11 @@ SEED_PERM = 2
 SEED_FIELDS = 3
 SEED_BATCH = 4
 SEED_ARRIVALS = 5
+SEED_MATERIAL = 6
+
+# Vertex triples of the four faces of a tetrahedron (v1..v4 = 0..3), the numbering of the
+# library interface: F1 = (v1,v2,v3), F2 = (v1,v2,v4), F3 = (v2,v3,v4), F4 = (v1,v3,v4).
+FACE_VERTS = ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3))
 
 # Axis orders (x=0, y=1, z=2) in lexicographic order; the Kuhn tetrahedron p walks the cube
 # diagonal along these axes.
@@ -130,24 +135,49 @@ def eval_smooth_fields(modes, x, y, z):
     return out
 
 
-def cavity_tm110(x, y, z, t: float):
-    """(1,1,0) TM eigenmode of the perfectly conducting unit-cube cavity, eps = mu = 1.
+def cavity_tm110(x, y, z, t: float, eps: float = 1.0, mu: float = 1.0):
+    """(1,1,0) TM eigenmode of the perfectly conducting unit-cube cavity filled with a uniform
+    medium (default vacuum, eps = mu = 1).
 
-    E = (0, 0, sin(pi x) sin(pi y) cos(w t)), w = pi*sqrt(2),
-    H = (-(pi/w) sin(pi x) cos(pi y) sin(w t), (pi/w) cos(pi x) sin(pi y) sin(w t), 0).
+    E = (0, 0, sin(pi x) sin(pi y) cos(w t)),  w = pi sqrt(2) / sqrt(eps mu),
+    H = (1/(Z w')) (-pi sin(pi x) cos(pi y), pi cos(pi x) sin(pi y), 0) sin(w t),
+    with Z = sqrt(mu/eps) and w' = pi sqrt(2) (it solves eps E_t = curl H, mu H_t = -curl E).
     Returns (6,) + x.shape float64 in the order Ex, Ey, Ez, Hx, Hy, Hz.
     """
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
-    w = math.pi * math.sqrt(2.0)
+    w0 = math.pi * math.sqrt(2.0)
+    w = w0 / math.sqrt(eps * mu)
+    zi = math.sqrt(eps / mu)          # 1 / Z
     out = np.zeros((6,) + x.shape, dtype=np.float64)
     sx, cx = np.sin(math.pi * x), np.cos(math.pi * x)
     sy, cy = np.sin(math.pi * y), np.cos(math.pi * y)
     out[2] = sx * sy * math.cos(w * t)
-    out[3] = -(math.pi / w) * sx * cy * math.sin(w * t)
-    out[4] = (math.pi / w) * cx * sy * math.sin(w * t)
+    out[3] = -zi * (math.pi / w0) * sx * cy * math.sin(w * t)
+    out[4] = zi * (math.pi / w0) * cx * sy * math.sin(w * t)
     return out
+
+
+def random_materials(K: int, seed: int = SEED_MATERIAL, lo: float = 1.0, hi: float = 4.0):
+    """Piecewise-constant permittivity and permeability, one value per element,
+    log-uniform in [lo, hi] (independent draws for eps and mu)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    eps = np.exp(g.uniform(math.log(lo), math.log(hi), K))
+    mu = np.exp(g.uniform(math.log(lo), math.log(hi), K))
+    return eps, mu
+
+
+def faces_on_plane(vxyz, etov, axis: int, value: float, tol: float = 1e-12):
+    """(K, 4) int8 mask of the element faces lying in the plane x_axis = value; face f of
+    element k is the vertex triple FACE_VERTS[f] of etov[k] as given."""
+    vxyz = np.asarray(vxyz, dtype=np.float64)
+    etov = np.asarray(etov)
+    on = np.abs(vxyz[:, axis] - value) <= tol
+    mask = np.zeros(etov.shape, dtype=np.int8)
+    for f, tri in enumerate(FACE_VERTS):
+        mask[:, f] = np.all(on[etov[:, list(tri)]], axis=1)
+    return mask
 
 
 def batch_specs(count: int = 64, seed: int = SEED_BATCH, kmin: float = 1e3, kmax: float = 5e4,

@@ -15,6 +15,9 @@ flux; alpha = 0 is the central flux, used only by the energy tests):
 which in vacuum is  1/2 (n x [H] + alpha([E] - (n.[E]) n))  and
                     1/2 (-n x [E] + alpha([H] - (n.[H]) n)).
 A perfectly conducting wall (Sec. 6 cavity) mirrors the trace: E+ = -E-, H+ = H-.
+An absorbing face (the characteristic absorbing condition named for the scattering example of
+Sec. 6) takes a zero exterior state, u+ = 0, with the exterior impedance equal to the interior
+one; the upwind flux then lets outgoing characteristics leave and admits nothing.
 
 Time stepping: the five-stage fourth-order 2N-storage Runge-Kutta method of Carpenter and
 Kennedy cited in Sec. 6: res <- a_i res + dt L(u); u <- u + b_i res.
@@ -71,14 +74,18 @@ def volume_term(mesh: Mesh, u):
     return _curl_term(mesh.ref, mesh.G, u)
 
 
-def _flux_terms(flat, vM, vP, bnd, nrm, alpha, imp):
+def _flux_terms(flat, vM, vP, bnd, nrm, alpha, imp, absorb=None):
     """[n.F - (n.F)*] at face nodes given flat fields (6, K*Np), maps vM/vP (k,4,Nfp),
-    wall flags bnd (k,4), normals nrm (k,4,3) and impedances imp = (zm, zp, ym, yp)."""
+    wall flags bnd (k,4), normals nrm (k,4,3), impedances imp = (zm, zp, ym, yp) and
+    absorbing-face flags absorb (k,4, a subset of the walls; None = none)."""
     uM = flat[:, vM]
     uP = flat[:, vP]
     b = bnd[:, :, None]
     # perfectly conducting wall: E+ = -E-, H+ = H-
     uP = np.where(b[None], np.concatenate([-uM[:3], uM[3:]]), uP)
+    if absorb is not None:
+        # absorbing face: zero exterior state
+        uP = np.where(np.asarray(absorb, dtype=bool)[None, :, :, None], 0.0, uP)
     dE = uP[:3] - uM[:3]
     dH = uP[3:] - uM[3:]
     n = np.moveaxis(nrm, 2, 0)[:, :, :, None]  # 3, k, 4, 1
@@ -101,12 +108,21 @@ def _impedances(mesh, elems, eps, mu):
     return zm, zp, 1.0 / zm, 1.0 / zp
 
 
-def surface_flux(mesh: Mesh, u, alpha=1.0, eps=None, mu=None):
+def _check_absorb(mesh: Mesh, absorb):
+    if absorb is None:
+        return None
+    absorb = np.asarray(absorb, dtype=bool)
+    assert absorb.shape == (mesh.K, 4) and not np.any(absorb & ~mesh.boundary), \
+        "absorbing flags must mark boundary faces"
+    return absorb
+
+
+def surface_flux(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
     """[n.F - (n.F)*] at every face node, (6, K, 4, Nfp), not yet scaled by Fscale."""
     K, Np = u.shape[1], u.shape[2]
     elems = np.arange(K)
     return _flux_terms(u.reshape(6, K * Np), mesh.vmapM, mesh.vmapP, mesh.boundary, mesh.n, alpha,
-                       _impedances(mesh, elems, eps, mu))
+                       _impedances(mesh, elems, eps, mu), _check_absorb(mesh, absorb))
 
 
 def _assemble(ref, vol, flux, Fscale, eps_k, mu_k):
@@ -120,10 +136,11 @@ def _assemble(ref, vol, flux, Fscale, eps_k, mu_k):
     return out
 
 
-def rhs(mesh: Mesh, u, alpha=1.0, eps=None, mu=None):
-    """Semi-discrete right-hand side du/dt, u of shape (6, K, Np), FP64."""
+def rhs(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
+    """Semi-discrete right-hand side du/dt, u of shape (6, K, Np), FP64. eps, mu: per-element
+    permittivity and permeability (None = 1); absorb: (K, 4) absorbing-face flags."""
     vol = volume_term(mesh, u)
-    flux = surface_flux(mesh, u, alpha, eps, mu)                    # 6, K, 4, Nfp
+    flux = surface_flux(mesh, u, alpha, eps, mu, absorb)            # 6, K, 4, Nfp
     e = None if eps is None else np.asarray(eps, dtype=np.float64)
     m = None if mu is None else np.asarray(mu, dtype=np.float64)
     return _assemble(mesh.ref, vol, flux, mesh.Fscale, e, m)

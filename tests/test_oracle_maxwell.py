@@ -108,12 +108,18 @@ def _flux_vol_dot_grad(uE, uH, g):
                      Ez * gy - Ey * gz, -Ez * gx + Ex * gz, Ey * gx - Ex * gy])
 
 
-def brute_force_operator(vxyz, etov, N):
-    """Weak form M du/dt = int F(u).grad l - int (n.F)* l on every element, assembled
-    with physical-space quadrature and the upwind flux of Sec. 6 (vacuum) written out."""
+def brute_force_operator(vxyz, etov, N, eps=None, mu=None, absorb=None):
+    """Weak form M (eps dE/dt, mu dH/dt) = int F(u).grad l - int (n.F)* l on every element,
+    assembled with physical-space quadrature and the upwind flux of Sec. 6 written out with
+    the impedances Z = sqrt(mu/eps), Y = 1/Z of both sides (vacuum by default). Unmatched
+    faces mirror the trace (wall), or take a zero exterior state where absorb[k][f] is set."""
     ref = R.ref_element(N)
     m = Mm.Mesh(vxyz, etov, ref, compute_maps=False)
     K, Np = m.K, ref.Np
+    eps = np.ones(K) if eps is None else np.asarray(eps, dtype=np.float64)
+    mu = np.ones(K) if mu is None else np.asarray(mu, dtype=np.float64)
+    Zk = np.sqrt(mu / eps)
+    absorb = np.zeros((K, 4), dtype=bool) if absorb is None else np.asarray(absorb, dtype=bool)
     bases = [_MonoBasis(N, m.x[:, k, :].T) for k in range(K)]
     qv, wv = tet_quadrature(N + 2)
     qf, wf = tri_quadrature(N + 2)
@@ -169,6 +175,8 @@ def brute_force_operator(vxyz, etov, N):
                         nb = kk
             Lp = bases[nb].val(xf) if nb is not None else None
             sources = [(k, Lm, -1)] + ([(nb, Lp, +1)] if nb is not None else [])
+            Zm = Zk[k]
+            Zp = Zk[nb] if nb is not None else Zk[k]
             for src, Ls, side in sources:
                 for g in range(6):
                     for j in range(Np):
@@ -176,19 +184,22 @@ def brute_force_operator(vxyz, etov, N):
                         up = np.zeros((6, xf.shape[0]))
                         if side < 0:
                             um[g] = Ls[:, j]
-                            if nb is None:          # perfectly conducting wall mirror
+                            if nb is None and not absorb[k][f]:   # wall mirror
                                 up[:3] = -um[:3]
                                 up[3:] = um[3:]
                         else:
                             up[g] = Ls[:, j]
                         dE, dH = up[:3] - um[:3], up[3:] - um[3:]
-                        # [n.F - (n.F)*] from Sec. 6 with Z = Y = 1
-                        bE = 0.5 * np.cross(nvq.T, (dH - np.cross(nvq.T, dE.T).T).T).T
-                        bH = 0.5 * np.cross(nvq.T, (-dE - np.cross(nvq.T, dH.T).T).T).T
+                        # [n.F - (n.F)*] from Sec. 6: {Z}^-1 / 2 = 1 / (Z- + Z+)
+                        bE = np.cross(nvq.T, (Zp * dH - np.cross(nvq.T, dE.T).T).T).T / (Zm + Zp)
+                        bH = np.cross(nvq.T, (-dE / Zp - np.cross(nvq.T, dH.T).T).T).T / (1 / Zm + 1 / Zp)
                         star = _flux_dot_n(nvq, um[:3], um[3:]) - np.concatenate([bE, bH])
                         face = (star[:, :, None] * Lm[None, :, :] * wfa[None, :, None]).sum(1)  # 6 x Np
                         col = g * K * Np + src * Np + j
                         A[np.concatenate([idx(ff_, k) for ff_ in range(6)]), col] -= (Minv @ face.T).T.ravel()
+    for k in range(K):
+        for f in range(6):
+            A[idx(f, k)] /= eps[k] if f < 3 else mu[k]
     return A, m
 
 

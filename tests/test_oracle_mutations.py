@@ -43,26 +43,26 @@ ORIG_VOLUME = W.volume_term
 ORIG_FLUX = W.surface_flux
 
 
-def _flux_wrong_normal(mesh, u, alpha=1.0, eps=None, mu=None):
+def _flux_wrong_normal(mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
     saved = mesh.n
     mesh.n = -saved
     try:
-        return ORIG_FLUX(mesh, u, alpha, eps, mu)
+        return ORIG_FLUX(mesh, u, alpha, eps, mu, absorb)
     finally:
         mesh.n = saved
 
 
-def _flux_no_neighbour(mesh, u, alpha=1.0, eps=None, mu=None):
+def _flux_no_neighbour(mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
     saved = mesh.vmapP
     mesh.vmapP = mesh.vmapM
     try:
-        return ORIG_FLUX(mesh, u, alpha, eps, mu)
+        return ORIG_FLUX(mesh, u, alpha, eps, mu, absorb)
     finally:
         mesh.vmapP = saved
 
 
-def _flux_half(mesh, u, alpha=1.0, eps=None, mu=None):
-    return 0.5 * ORIG_FLUX(mesh, u, alpha, eps, mu)
+def _flux_half(mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
+    return 0.5 * ORIG_FLUX(mesh, u, alpha, eps, mu, absorb)
 
 
 @pytest.mark.parametrize("name,target,replacement", [
@@ -95,3 +95,47 @@ def test_anti_dissipative_flux_is_caught():
     Mw = mass_weight(m)
     S = Mw @ A + A.T @ Mw
     assert np.max(np.linalg.eigvalsh(S)) > 1e-6 * np.linalg.norm(Mw @ A)
+
+
+# ---------------------------------------------------------------------------------------
+# heterogeneous medium and absorbing faces
+
+EPS = np.array([2.0, 1.3])
+MU = np.array([1.5, 3.0])
+
+
+def _material_case():
+    etov = Mm.orient(VXYZ, ETOV)
+    mo = Mm.Mesh(VXYZ, etov, R.ref_element(N))
+    absorb = np.zeros((2, 4), dtype=bool)
+    bf = np.argwhere(mo.boundary)
+    absorb[tuple(bf[0])] = True
+    absorb[tuple(bf[-1])] = True
+    A_bf, _ = brute_force_operator(VXYZ, etov, N, eps=EPS, mu=MU, absorb=absorb)
+    return mo, absorb, A_bf
+
+
+ORIG_IMP = W._impedances
+ORIG_ASSEMBLE = W._assemble
+
+
+def _impedances_swapped(mesh, elems, eps, mu):
+    zm, zp, ym, yp = ORIG_IMP(mesh, elems, eps, mu)
+    return zp, zm, yp, ym
+
+
+def _assemble_without_mu(ref, vol, flux, Fscale, eps_k, mu_k):
+    return ORIG_ASSEMBLE(ref, vol, flux, Fscale, eps_k, None)
+
+
+@pytest.mark.parametrize("name,target,replacement", [
+    ("interior and exterior impedances exchanged", "_impedances", _impedances_swapped),
+    ("absorbing faces treated as walls", "_check_absorb", lambda mesh, absorb: None),
+    ("H rows not divided by mu", "_assemble", _assemble_without_mu),
+])
+def test_planted_material_mistake_is_caught(monkeypatch, name, target, replacement):
+    mo, absorb, A_bf = _material_case()
+    assert np.linalg.norm(assemble(mo, eps=EPS, mu=MU, absorb=absorb) - A_bf) < 1e-11 * np.linalg.norm(A_bf)
+    monkeypatch.setattr(W, target, replacement)
+    A = assemble(mo, eps=EPS, mu=MU, absorb=absorb)
+    assert np.linalg.norm(A - A_bf) > 1e-3 * np.linalg.norm(A_bf), name
