@@ -4,9 +4,11 @@
  *
  * The library evaluates the semi-discrete DG operator of the paper's Sec. 2
  * (eq. semidiscrete-dg: du/dt = -sum_nu D^nu F(u) + L[n.F - (n.F)*]) for Maxwell's equations
- * in vacuum (Sec. 6, eq. maxwells-claws, eps = mu = 1) with the upwind flux of Sec. 6 and
- * perfectly conducting walls (mirror state E+ = -E-, H+ = H-), and advances it with the
- * five-stage fourth-order low-storage Runge-Kutta method named in Sec. 6.
+ * (Sec. 6, eq. maxwells-claws) in vacuum or in a medium with piecewise-constant eps and mu,
+ * with the impedance-weighted upwind flux of Sec. 6, perfectly conducting walls (mirror state
+ * E+ = -E-, H+ = H-) and absorbing faces (zero exterior state, the characteristic absorbing
+ * condition named for the scattering example of Sec. 6), and advances it with the five-stage
+ * fourth-order low-storage Runge-Kutta method named in Sec. 6.
  *
  * Conventions
  *   Fields: six components in the order Ex, Ey, Ez, Hx, Hy, Hz.
@@ -37,7 +39,7 @@ extern "C" {
 #define DG_OK 0
 #define DG_E_ARG (-1)         /* invalid argument (NULL pointer, bad size, bad option) */
 #define DG_E_MESH (-2)        /* invalid mesh: degenerate element, face shared by > 2 elements */
-#define DG_E_UNSUPPORTED (-3) /* order outside 1..7, unknown precision, non-vacuum material */
+#define DG_E_UNSUPPORTED (-3) /* order outside 1..7, unknown precision */
 #define DG_E_OOM (-4)         /* device allocation failed or the workspace is too small */
 #define DG_E_HIP (-5)         /* a HIP runtime call failed; message in dg_last_error() */
 #define DG_E_STATE (-6)       /* handle has no device state (built with device = -1) */
@@ -53,11 +55,13 @@ typedef struct {
   const double* vxyz;     /* nverts x 3, row-major coordinates */
   int32_t K;              /* number of tetrahedra, 1 <= K < 2^26 */
   const int32_t* etov;    /* K x 4 vertex ids, 0-based, any orientation */
-  const int8_t* face_bc;  /* K x 4 or NULL: 0 = automatic (unmatched faces are perfectly
-                             conducting walls), 1 = wall; nonzero on a matched face is an
-                             error */
-  const double* eps;      /* must be NULL (vacuum) */
-  const double* mu;       /* must be NULL (vacuum) */
+  const int8_t* face_bc;  /* K x 4 or NULL, face f of element k being the triple F(f+1) of
+                             etov[k] as given (before the orientation fix): 0 = automatic
+                             (an unmatched face is a perfectly conducting wall), 1 = wall,
+                             2 = absorbing; nonzero on a matched face is DG_E_MESH */
+  const double* eps;      /* K permittivities (> 0, finite) or NULL (= 1 everywhere) */
+  const double* mu;       /* K permeabilities (> 0, finite) or NULL (= 1 everywhere);
+                             a bad value is DG_E_ARG */
 } dg_mesh;
 
 typedef struct {
@@ -132,12 +136,13 @@ int dg_rk_step(dg_handle* h, double dt, void* stream);
 /* nsteps calls of dg_rk_step, launched from a captured HIP graph of two steps. */
 int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream);
 
-/* Discrete energy 1/2 sum_k J_k sum_fields u_k^T M u_k of the state, accumulated in double.
+/* Discrete energy 1/2 sum_k J_k (eps_k E_k^T M E_k + mu_k H_k^T M H_k) of the state (each
+ * field component separately; eps = mu = 1 in vacuum), accumulated in double.
  * Synchronises `stream`. */
 int dg_energy(const dg_handle* h, double* energy, void* stream);
 
 /* Time-step bound used by the tests and the benchmark: cfl * min over faces of 1/Fscale,
- * divided by N^2 (host-only). */
+ * divided by N^2 (host-only). It assumes wave speed at most 1, i.e. eps * mu >= 1. */
 int dg_stable_dt(const dg_handle* h, double cfl, double* dt);
 
 #ifdef __cplusplus

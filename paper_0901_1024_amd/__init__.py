@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libdg.so")
 
 DG_F64 = 0
 DG_F32 = 1
+DG_E_ARG = -1
 _PREC = {"f64": DG_F64, "f32": DG_F32}
 _ERRS = {-1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_UNSUPPORTED", -4: "DG_E_OOM", -5: "DG_E_HIP",
          -6: "DG_E_STATE"}
@@ -97,7 +98,7 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-def _mesh_struct(vxyz, etov, face_bc=None):
+def _mesh_struct(vxyz, etov, face_bc=None, eps=None, mu=None):
     vxyz = np.ascontiguousarray(vxyz, dtype=np.float64)
     etov = np.ascontiguousarray(etov, dtype=np.int32)
     m = _Mesh()
@@ -108,8 +109,17 @@ def _mesh_struct(vxyz, etov, face_bc=None):
     keep = [vxyz, etov]
     if face_bc is not None:
         fb = np.ascontiguousarray(face_bc, dtype=np.int8)
+        if fb.shape != (m.K, 4):
+            raise DGError(DG_E_ARG, "face_bc must have shape (K, 4)")
         m.face_bc = _ptr(fb, ctypes.c_int8)
         keep.append(fb)
+    for name, arr in (("eps", eps), ("mu", mu)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64)
+            if a.shape != (m.K,):
+                raise DGError(DG_E_ARG, f"{name} must have shape (K,)")
+            setattr(m, name, _ptr(a, ctypes.c_double))
+            keep.append(a)
     return m, keep
 
 
@@ -122,8 +132,8 @@ def _opts_struct(order, precision, reorder, device):
     return o
 
 
-def setup_query(vxyz, etov, order, precision="f64", reorder=1):
-    m, _keep = _mesh_struct(vxyz, etov)
+def setup_query(vxyz, etov, order, precision="f64", reorder=1, eps=None, mu=None):
+    m, _keep = _mesh_struct(vxyz, etov, eps=eps, mu=mu)
     o = _opts_struct(order, precision, reorder, 0)
     n = ctypes.c_size_t()
     _check(lib().dg_setup_query(ctypes.byref(m), ctypes.byref(o), ctypes.byref(n)))
@@ -141,15 +151,16 @@ class Solver:
 
     device >= 0: the workspace is a torch uint8 tensor on cuda:device (PyTorch owns the HBM);
     device = -1: host-only handle (builder outputs only).
+    face_bc: (K, 4) int8, 0 automatic, 1 wall, 2 absorbing; eps, mu: (K,) per element.
     """
 
     def __init__(self, vxyz, etov, order, precision="f64", reorder=1, device=0, face_bc=None,
-                 stream=None):
+                 stream=None, eps=None, mu=None):
         L = lib()
         self.order = order
         self.precision = precision
         self.device = device
-        m, keep = _mesh_struct(vxyz, etov, face_bc)
+        m, keep = _mesh_struct(vxyz, etov, face_bc, eps, mu)
         o = _opts_struct(order, precision, reorder, device)
         h = ctypes.c_void_p()
         self._ws = None

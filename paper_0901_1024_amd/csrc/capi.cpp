@@ -35,8 +35,8 @@ constexpr double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 /
 struct Layout {
   size_t state = 0;  // bytes of one [K][6][Np] array
   size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
-      off_elem_of, off_pos_of, off_partial, off_opcat, total;
-  size_t opcat_bytes = 0;
+      off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, total;
+  size_t opcat_bytes = 0, mat_bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -44,7 +44,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // The fragment-ordered concatenated operator is used by the FP32 contraction kernels only.
 int opfrag_words_for(int N, size_t ts) { return (ts == 4 && dgk::mfma_order(N)) ? dgk::opcat_words(N) : 0; }
 
-Layout make_layout(int K, int N, int Np, int Nfp, size_t ts) {
+Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -67,6 +67,8 @@ Layout make_layout(int K, int N, int Np, int Nfp, size_t ts) {
   L.off_partial = take(size_t((K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems) * sizeof(double));
   L.opcat_bytes = size_t(opfrag_words_for(N, ts)) * ts;
   L.off_opcat = take(L.opcat_bytes);
+  L.mat_bytes = material ? size_t(K) * dgh::kMatStride * ts : 0;
+  L.off_mat = take(L.mat_bytes);
   L.total = o;
   return L;
 }
@@ -78,7 +80,6 @@ int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
   if (opts->order < 1 || opts->order > 7) return fail(DG_E_UNSUPPORTED, "order must be in 1..7");
   if (opts->precision != DG_F64 && opts->precision != DG_F32)
     return fail(DG_E_UNSUPPORTED, "unknown precision");
-  if (mesh->eps || mesh->mu) return fail(DG_E_UNSUPPORTED, "only vacuum (eps = mu = NULL) is supported");
   if (opts->reorder < 0 || opts->reorder > 1) return fail(DG_E_ARG, "reorder must be 0 or 1");
   return DG_OK;
 }
@@ -88,6 +89,7 @@ int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
 struct dg_handle {
   dgh::RefOps ref;
   dgh::MeshData mesh;
+  std::vector<double> mat;   // material records (internal order); empty in vacuum
   int N = 0, Np = 0, Nfp = 0, K = 0, prec = 0, device = -1;
   size_t ts = 8;
   Layout lay;
@@ -184,6 +186,11 @@ int upload(dg_handle* h, hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
   }
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_geo), geo_b.data(), geo_b.size(), hipMemcpyHostToDevice, s));
+  std::vector<char> mat_b;
+  if (h->lay.mat_bytes) {
+    mat_b = to_prec(h->mat, h->f64());
+    HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_mat), mat_b.data(), mat_b.size(), hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_ops), ops_b.data(), ops_b.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_fcode), M.face_code.data(), M.face_code.size() * 4,
                          hipMemcpyHostToDevice, s));
@@ -218,6 +225,7 @@ int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, 
   args.res = h->at(h->lay.off_res);
   args.geo = h->at(h->lay.off_geo);
   args.fcode = static_cast<const int32_t*>(h->at(h->lay.off_fcode));
+  args.mat = h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr;
   args.K = h->K;
   args.a = a;
   args.b = b;
@@ -247,7 +255,8 @@ int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_b
   if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
   const int N = opts->order;
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
-  *workspace_bytes = make_layout(mesh->K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4).total;
+  *workspace_bytes =
+      make_layout(mesh->K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4, mesh->eps || mesh->mu).total;
   return DG_OK;
 }
 
@@ -268,6 +277,15 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
   } catch (const std::exception& ex) {
     return fail(DG_E_MESH, ex.what());
   }
+  if (mesh->eps || mesh->mu) {
+    try {
+      h->mat = dgh::material_records(h->mesh, mesh->eps, mesh->mu);
+    } catch (const std::bad_alloc&) {
+      return fail(DG_E_OOM, "host allocation failed");
+    } catch (const std::exception& ex) {
+      return fail(DG_E_ARG, ex.what());
+    }
+  }
   h->N = opts->order;
   h->Np = h->ref.Np;
   h->Nfp = h->ref.Nfp;
@@ -275,7 +293,7 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
   h->prec = opts->precision;
   h->ts = h->f64() ? 8 : 4;
   h->device = opts->device;
-  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts);
+  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty());
   if (h->device >= 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());
@@ -465,7 +483,8 @@ int dg_energy(const dg_handle* h, double* energy, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nb = (h->K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems;
   double* partial = static_cast<double*>(h->at(h->lay.off_partial));
-  HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo), h->K, partial, s));
+  HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo),
+                             h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr, h->K, partial, s));
   std::vector<double> host(nb);
   HIP_TRY(hipMemcpyAsync(host.data(), partial, nb * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -33,7 +33,9 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
   for (int64_t q = 0; q < int64_t(K) * 4; ++q)
     if (m.etov[q] < 0 || m.etov[q] >= nverts) throw std::runtime_error("vertex id out of range");
 
-  // Orientation: det[v2-v1, v3-v1, v4-v1] must be positive; a negative one swaps v3 and v4.
+  // Orientation: det[v2-v1, v3-v1, v4-v1] must be positive; a negative one swaps v3 and v4
+  // (which exchanges the faces F1 = (v1,v2,v3) and F2 = (v1,v2,v4)).
+  std::vector<uint8_t> swapped(K, 0);
   for (int k = 0; k < K; ++k) {
     const double* p[4];
     for (int v = 0; v < 4; ++v) p[v] = vxyz + 3 * size_t(m.etov[size_t(k) * 4 + v]);
@@ -42,7 +44,10 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
     double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
                  a[2] * (b[0] * c[1] - b[1] * c[0]);
     if (det == 0.0 || !std::isfinite(det)) throw std::runtime_error("degenerate element");
-    if (det < 0.0) std::swap(m.etov[size_t(k) * 4 + 2], m.etov[size_t(k) * 4 + 3]);
+    if (det < 0.0) {
+      std::swap(m.etov[size_t(k) * 4 + 2], m.etov[size_t(k) * 4 + 3]);
+      swapped[k] = 1;
+    }
   }
 
   // Connectivity: sort faces by their sorted vertex triple; equal neighbours pair up.
@@ -80,12 +85,18 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
     }
     q = e;
   }
+  m.absorbing.assign(size_t(K) * 4, 0);
   if (face_bc) {
-    for (int64_t q = 0; q < int64_t(K) * 4; ++q) {
-      bool boundary = m.etoe[q] == q / 4 && m.etof[q] == q % 4;
-      if (face_bc[q] < 0 || face_bc[q] > 1) throw std::runtime_error("unsupported face condition");
-      if (face_bc[q] != 0 && !boundary) throw std::runtime_error("wall condition on an interior face");
-    }
+    for (int k = 0; k < K; ++k)
+      for (int fu = 0; fu < 4; ++fu) {
+        const int8_t bc = face_bc[size_t(k) * 4 + fu];
+        const int f = swapped[k] && fu < 2 ? 1 - fu : fu;   // the user's face in internal numbering
+        const size_t q = size_t(k) * 4 + f;
+        const bool boundary = m.etoe[q] == k && m.etof[q] == f;
+        if (bc < 0 || bc > 2) throw std::runtime_error("unsupported face condition");
+        if (bc != 0 && !boundary) throw std::runtime_error("boundary condition on an interior face");
+        m.absorbing[q] = bc == 2;
+      }
   }
 
   // Orientation code of each interior face: my face vertex a is the neighbour's face vertex
@@ -203,10 +214,40 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
     for (int f = 0; f < 4; ++f) {
       size_t q = size_t(k) * 4 + f;
       m.face_code[size_t(i) * 4 + f] =
-          (m.orient[q] < 0) ? -1 : pack_face(m.pos_of[m.etoe[q]], m.orient[q], m.etof[q]);
+          (m.orient[q] >= 0) ? pack_face(m.pos_of[m.etoe[q]], m.orient[q], m.etof[q])
+                             : (m.absorbing[q] ? kFaceAbsorbing : kFacePec);
     }
   }
   return m;
+}
+
+std::vector<double> material_records(const MeshData& m, const double* eps, const double* mu) {
+  const int K = m.K;
+  std::vector<double> Z(K);
+  for (int k = 0; k < K; ++k) {
+    const double e = eps ? eps[k] : 1.0, u = mu ? mu[k] : 1.0;
+    if (!(std::isfinite(e) && e > 0.0 && std::isfinite(u) && u > 0.0))
+      throw std::runtime_error("eps and mu must be finite and positive");
+    Z[k] = std::sqrt(u / e);
+  }
+  std::vector<double> rec(size_t(K) * kMatStride);
+  for (int i = 0; i < K; ++i) {
+    const int k = m.elem_of[i];
+    const double e = eps ? eps[k] : 1.0, u = mu ? mu[k] : 1.0;
+    double* r = &rec[size_t(i) * kMatStride];
+    r[0] = 1.0 / e, r[1] = 1.0 / u, r[2] = e, r[3] = u;
+    for (int f = 0; f < 4; ++f) {
+      const size_t q = size_t(k) * 4 + f;
+      const double fs = m.geo[size_t(k) * kGeoStride + kGeoNormal + 4 * f + 3];
+      const double zm = Z[k], zp = m.orient[q] >= 0 ? Z[m.etoe[q]] : zm;
+      const double ym = 1.0 / zm, yp = 1.0 / zp;
+      r[kMatFace + 4 * f + 0] = fs / e * zp / (zm + zp);
+      r[kMatFace + 4 * f + 1] = fs / e / (zm + zp);
+      r[kMatFace + 4 * f + 2] = fs / u * yp / (ym + yp);
+      r[kMatFace + 4 * f + 3] = fs / u / (ym + yp);
+    }
+  }
+  return rec;
 }
 
 void canonical_maps(const RefOps& R, const MeshData& m, int32_t* vmapM, int32_t* vmapP) {

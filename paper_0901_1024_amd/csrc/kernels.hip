@@ -41,10 +41,10 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 template <typename T, int N, bool STAGE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(
     const T* __restrict__ u_in, T* __restrict__ out, T* __restrict__ res,
-    const T* __restrict__ geo, const int32_t* __restrict__ fcode, const T* __restrict__ Dr,
-    const T* __restrict__ Ds, const T* __restrict__ Dt, const T* __restrict__ LIFT,
-    const int32_t* __restrict__ fmask, const int32_t* __restrict__ nbrnode, int K, int ntiles,
-    T ca, T cb, T cdt) {
+    const T* __restrict__ geo, const int32_t* __restrict__ fcode, const T* __restrict__ mat,
+    const T* __restrict__ Dr, const T* __restrict__ Ds, const T* __restrict__ Dt,
+    const T* __restrict__ LIFT, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, T ca, T cb, T cdt) {
   using D = Dims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E;
   constexpr int G = dgh::kGeoStride;
@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
   for (int q = threadIdx.x; q < nel * 6 * NP; q += kThreads) us[q] = src[q];
   __syncthreads();
 
-  // face fluxes, already multiplied by Fscale / 2 (the upwind flux carries a factor 1/2)
+  // face fluxes, already multiplied by Fscale / 2 (the upwind flux carries a factor 1/2), or
+  // in a heterogeneous medium by the folded impedance weights of the material record
   for (int q = threadIdx.x; q < nel * NF4; q += kThreads) {
     const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
     const int elem = base + e;
@@ -71,9 +72,12 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
     const T Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
     T dEx, dEy, dEz, dHx, dHy, dHz;
     const int code = fcode[size_t(elem) * 4 + f];
-    if (code < 0) {  // perfectly conducting wall: E+ = -E-, H+ = H-
+    if (code == dgh::kFacePec) {   // perfectly conducting wall: E+ = -E-, H+ = H-
       dEx = T(-2) * Ex, dEy = T(-2) * Ey, dEz = T(-2) * Ez;
       dHx = dHy = dHz = T(0);
+    } else if (code < 0) {         // absorbing face: zero exterior state
+      dEx = -Ex, dEy = -Ey, dEz = -Ez;
+      dHx = -Hx, dHy = -Hy, dHz = -Hz;
     } else {
       const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
       const int nn = nbrnode[((f * 4 + f2) * 6 + o) * NFP + j];
@@ -85,6 +89,17 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
     const T ndE = nx * dEx + ny * dEy + nz * dEz;
     const T ndH = nx * dHx + ny * dHy + nz * dHz;
     T* o = fl + e * 6 * NF4 + fj;
+    if (mat) {
+      const T* w = mat + size_t(elem) * dgh::kMatStride + dgh::kMatFace + 4 * f;
+      const T A = w[0], B = w[1], C = w[2], Dd = w[3];
+      o[0 * NF4] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
+      o[1 * NF4] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
+      o[2 * NF4] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
+      o[3 * NF4] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
+      o[4 * NF4] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
+      o[5 * NF4] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
+      continue;
+    }
     o[0 * NF4] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
     o[1 * NF4] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
     o[2 * NF4] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
@@ -127,6 +142,10 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
     r[3] = -(dy[2] - dz[1]);   // -(curl E)_x
     r[4] = -(dz[0] - dx[2]);   // -(curl E)_y
     r[5] = -(dx[1] - dy[0]);   // -(curl E)_z
+    if (mat) {                 // 1/eps, 1/mu (the lifted fluxes carry them already)
+      const T ie = mat[size_t(elem) * dgh::kMatStride], im = mat[size_t(elem) * dgh::kMatStride + 1];
+      r[0] *= ie, r[1] *= ie, r[2] *= ie, r[3] *= im, r[4] *= im, r[5] *= im;
+    }
     const T* fe = fl + e * 6 * NF4;
     for (int fj = 0; fj < NF4; ++fj) {
       const T l = LIFT[n * NF4 + fj];
@@ -212,10 +231,13 @@ struct MDims {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int N, bool STAGE>
+// MAT: heterogeneous medium. 1/eps and 1/mu of the tile's elements ride in the unused last
+// words of each element row of the padded copy (up_s) and scale the operand coefficients;
+// the face weights (material record) are read with the neighbour traces.
+template <int N, bool STAGE, bool MAT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void mfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
-    const float* __restrict__ geo, const int32_t* __restrict__ fcode,
+    const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
     const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
   using D = MDims<N>;
@@ -263,6 +285,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   floatx4 pu[CPT];
   float pg[GPT];
   int32_t pf = 0;
+  float pm = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
   // Inlined so that the prefetch arrays stay in registers. Every thread loads every slot
   // (indices clamped into the tile): exec-masked loads make the compiler wait for all
   // outstanding loads before reusing their registers.
@@ -274,6 +297,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * kThreads, GW - 1)];
       pf = fcode[size_t(t) * E * 4 + min(tid, E * 4 - 1)];
+      if (MAT) {
+        const int q = min(tid, 2 * E - 1);
+        pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
+      }
     }
   };
   prefetch(tile);
@@ -297,8 +324,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (q < GW) gt[q] = pg[r];
       }
       if (tid < E * 4) fc[tid] = pf;
+      if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
     } else {
       for (int q = tid; q < nel * 6 * NP; q += kThreads) us[q] = u_in[tb + q];
+      if (MAT)
+        for (int q = tid; q < 2 * nel; q += kThreads)
+          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
       for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
       for (int q = tid; q < nel * 4; q += kThreads) fc[q] = fcode[size_t(base) * 4 + q];
     }
@@ -309,11 +340,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     // ---- face fluxes: fetch every neighbour trace first, then compute
     {
       float up[FIT][6];
+      floatx4 wm[FIT];   // MAT: face weights A B C D
 #pragma unroll
       for (int r = 0; r < FIT; ++r) {
         const int q = tid + r * kThreads;
         if (q < nel * NF4) {
           const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          if (MAT)
+            wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
+                                                      dgh::kMatFace + 4 * f);
           const int code = fc[e * 4 + f];
           if (code >= 0) {
             const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
@@ -357,9 +392,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
           const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
           float dEx, dEy, dEz, dHx, dHy, dHz;
-          if (fc[e * 4 + f] < 0) {   // perfectly conducting wall: E+ = -E-, H+ = H-
+          const int code = fc[e * 4 + f];
+          if (code == dgh::kFacePec) {   // perfectly conducting wall: E+ = -E-, H+ = H-
             dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
             dHx = dHy = dHz = 0.f;
+          } else if (code < 0) {         // absorbing face: zero exterior state
+            dEx = -Ex, dEy = -Ey, dEz = -Ez;
+            dHx = -Hx, dHy = -Hy, dHz = -Hz;
           } else {
             dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
             dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
@@ -367,12 +406,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           const float ndE = nx * dEx + ny * dEy + nz * dEz;
           const float ndH = nx * dHx + ny * dHy + nz * dHz;
           float* o = gl + e * RSL + fj;
-          o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
-          o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
-          o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
-          o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
-          o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
-          o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+          if (MAT) {
+            const float A = wm[r].x, B = wm[r].y, C = wm[r].z, Dd = wm[r].w;
+            o[0 * E * RSL] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
+            o[1 * E * RSL] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
+            o[2 * E * RSL] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
+            o[3 * E * RSL] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
+            o[4 * E * RSL] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
+            o[5 * E * RSL] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
+          } else {
+            o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
+            o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
+            o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
+            o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
+            o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
+            o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+          }
         }
       }
     }
@@ -403,10 +452,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
         const float sg = f < 3 ? 1.f : -1.f;
         const float* cm = gt + li * G;
+        // MAT: 1/eps on the E rows, 1/mu on the H rows
+        const float sm = MAT ? sg * up_s[li * ES + 6 * NPP + (f < 3 ? 0 : 1)] : sg;
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu) {
-          pc[t][mu] = sg * cm[3 * mu + b];
-          qc[t][mu] = -sg * cm[3 * mu + c];
+          pc[t][mu] = sm * cm[3 * mu + b];
+          qc[t][mu] = -sm * cm[3 * mu + c];
         }
         vc[t] = up_s + li * ES + (srcf + c) * NPP;
         vb[t] = up_s + li * ES + (srcf + b) * NPP;
@@ -586,25 +637,23 @@ int persistent_grid(Kern kern, int ntiles) {
   return want < cached ? want : cached;
 }
 
-template <int N>
-hipError_t launch_mfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
+template <int N, bool STAGE, bool MAT>
+hipError_t launch_mfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = MDims<N>::E;
   const int ntiles = (a.K + E - 1) / E;
-  auto* u = static_cast<const float*>(a.u_in);
-  auto* o = static_cast<float*>(a.out);
-  auto* r = static_cast<float*>(a.res);
-  auto* g = static_cast<const float*>(a.geo);
-  auto* oc = static_cast<const float*>(ops.opfrag);
-  if (stage) {
-    const int nb = persistent_grid(mfma_stage_kernel<N, true>, ntiles);
-    mfma_stage_kernel<N, true><<<nb, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
-                                                       a.K, ntiles, float(a.a), float(a.b), float(a.dt));
-  } else {
-    const int nb = persistent_grid(mfma_stage_kernel<N, false>, ntiles);
-    mfma_stage_kernel<N, false><<<nb, kThreads, 0, s>>>(u, o, r, g, a.fcode, oc, ops.fmask, ops.nbrnode,
-                                                        a.K, ntiles, 0.f, 0.f, 0.f);
-  }
+  const int nb = persistent_grid(mfma_stage_kernel<N, STAGE, MAT>, ntiles);
+  mfma_stage_kernel<N, STAGE, MAT><<<nb, kThreads, 0, s>>>(
+      static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
+      static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
+      static_cast<const float*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
+      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_mfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  if (a.mat) return stage ? launch_mfma_v<N, true, true>(ops, a, s) : launch_mfma_v<N, false, true>(ops, a, s);
+  return stage ? launch_mfma_v<N, true, false>(ops, a, s) : launch_mfma_v<N, false, false>(ops, a, s);
 }
 
 template <typename T, int N>
@@ -616,15 +665,16 @@ hipError_t launch_stage_t(bool stage, const OpsView& ops, const StageArgs& a, hi
   auto* o = static_cast<T*>(a.out);
   auto* r = static_cast<T*>(a.res);
   auto* g = static_cast<const T*>(a.geo);
+  auto* mt = static_cast<const T*>(a.mat);
   auto* dr = static_cast<const T*>(ops.Dr);
   auto* ds = static_cast<const T*>(ops.Ds);
   auto* dt = static_cast<const T*>(ops.Dt);
   auto* lf = static_cast<const T*>(ops.LIFT);
   if (stage)
-    stage_kernel<T, N, true><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, dr, ds, dt, lf, ops.fmask,
+    stage_kernel<T, N, true><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, mt, dr, ds, dt, lf, ops.fmask,
                                                          ops.nbrnode, a.K, ntiles, T(a.a), T(a.b), T(a.dt));
   else
-    stage_kernel<T, N, false><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, dr, ds, dt, lf, ops.fmask,
+    stage_kernel<T, N, false><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, mt, dr, ds, dt, lf, ops.fmask,
                                                           ops.nbrnode, a.K, ntiles, T(0), T(0), T(0));
   return hipGetLastError();
 }
@@ -658,8 +708,8 @@ __global__ void to_canonical_kernel(const T* __restrict__ internal, T* __restric
 
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void energy_kernel(const T* __restrict__ u, const T* __restrict__ M,
-                                                          const T* __restrict__ geo, int K,
-                                                          double* __restrict__ partial) {
+                                                          const T* __restrict__ geo, const T* __restrict__ mat,
+                                                          int K, double* __restrict__ partial) {
   constexpr int NP = Dims<N>::Np;
   __shared__ double red[kThreads];
   double acc = 0.0;
@@ -672,7 +722,9 @@ __global__ __launch_bounds__(kThreads) void energy_kernel(const T* __restrict__ 
     for (int c = 0; c < 6; ++c) {
       double mu = 0.0;
       for (int j = 0; j < NP; ++j) mu += double(M[i * NP + j]) * double(ue[c * NP + j]);
-      s += mu * double(ue[c * NP + i]);
+      // eps weights the E fields and mu the H fields in a medium
+      const double w = mat ? double(mat[size_t(e) * dgh::kMatStride + (c < 3 ? 2 : 3)]) : 1.0;
+      s += w * mu * double(ue[c * NP + i]);
     }
     acc += 0.5 * double(geo[size_t(e) * dgh::kGeoStride + dgh::kGeoJ]) * s;
   }
@@ -686,11 +738,12 @@ __global__ __launch_bounds__(kThreads) void energy_kernel(const T* __restrict__ 
 }
 
 template <typename T, int N>
-hipError_t launch_energy_t(const void* u, const void* M, const void* geo, int K, double* partial,
-                           hipStream_t s) {
+hipError_t launch_energy_t(const void* u, const void* M, const void* geo, const void* mat, int K,
+                           double* partial, hipStream_t s) {
   const int nb = (K + kEnergyBlockElems - 1) / kEnergyBlockElems;
   energy_kernel<T, N><<<nb, kThreads, 0, s>>>(static_cast<const T*>(u), static_cast<const T*>(M),
-                                              static_cast<const T*>(geo), K, partial);
+                                              static_cast<const T*>(geo), static_cast<const T*>(mat), K,
+                                              partial);
   return hipGetLastError();
 }
 
@@ -709,16 +762,16 @@ hipError_t dispatch_stage(int N, bool stage, const OpsView& o, const StageArgs& 
 }
 
 template <typename T>
-hipError_t dispatch_energy(int N, const void* u, const void* M, const void* geo, int K, double* p,
-                           hipStream_t s) {
+hipError_t dispatch_energy(int N, const void* u, const void* M, const void* geo, const void* mat, int K,
+                           double* p, hipStream_t s) {
   switch (N) {
-    case 1: return launch_energy_t<T, 1>(u, M, geo, K, p, s);
-    case 2: return launch_energy_t<T, 2>(u, M, geo, K, p, s);
-    case 3: return launch_energy_t<T, 3>(u, M, geo, K, p, s);
-    case 4: return launch_energy_t<T, 4>(u, M, geo, K, p, s);
-    case 5: return launch_energy_t<T, 5>(u, M, geo, K, p, s);
-    case 6: return launch_energy_t<T, 6>(u, M, geo, K, p, s);
-    case 7: return launch_energy_t<T, 7>(u, M, geo, K, p, s);
+    case 1: return launch_energy_t<T, 1>(u, M, geo, mat, K, p, s);
+    case 2: return launch_energy_t<T, 2>(u, M, geo, mat, K, p, s);
+    case 3: return launch_energy_t<T, 3>(u, M, geo, mat, K, p, s);
+    case 4: return launch_energy_t<T, 4>(u, M, geo, mat, K, p, s);
+    case 5: return launch_energy_t<T, 5>(u, M, geo, mat, K, p, s);
+    case 6: return launch_energy_t<T, 6>(u, M, geo, mat, K, p, s);
+    case 7: return launch_energy_t<T, 7>(u, M, geo, mat, K, p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -847,10 +900,10 @@ hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, cons
   return hipGetLastError();
 }
 
-hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, int K,
-                         double* partial, hipStream_t s) {
-  return f64 ? dispatch_energy<double>(N, u, M, geo, K, partial, s)
-             : dispatch_energy<float>(N, u, M, geo, K, partial, s);
+hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, const void* mat,
+                         int K, double* partial, hipStream_t s) {
+  return f64 ? dispatch_energy<double>(N, u, M, geo, mat, K, partial, s)
+             : dispatch_energy<float>(N, u, M, geo, mat, K, partial, s);
 }
 
 }  // namespace dgk

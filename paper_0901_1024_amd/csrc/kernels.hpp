@@ -37,6 +37,7 @@ struct StageArgs {
   void* res;         // RK residual, internal layout (stage mode only)
   const void* geo;   // [K][26]
   const int32_t* fcode;  // [K][4]
+  const void* mat;   // [K][20] material records of a heterogeneous medium, or NULL (vacuum)
   int K;
   double a, b, dt;   // stage coefficients (stage mode only)
 };
@@ -58,7 +59,7 @@ hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, cons
 // Partial energies: one double per block of `energy_block_elems` elements written to
 // `partial`; the caller sums them.
 constexpr int kEnergyBlockElems = 64;
-hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, int K,
-                         double* partial, hipStream_t s);
+hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, const void* mat,
+                         int K, double* partial, hipStream_t s);
 
 }  // namespace dgk

@@ -96,3 +96,28 @@ def test_errors_are_reported_not_raised_in_c():
 
 class _NullStream:
     cuda_stream = 0
+
+
+def test_material_and_face_condition_errors():
+    v, e = dginputs.kuhn_cube(1)
+    K = e.shape[0]
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        P.Solver(v, e, 2, device=-1, eps=-np.ones(K))
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        P.Solver(v, e, 2, device=-1, mu=np.full(K, np.nan))
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        P.Solver(v, e, 2, device=-1, eps=np.ones(K + 1))
+    fb = dginputs.faces_on_plane(v, e, 2, 1.0) * 2       # absorbing top faces: accepted
+    P.Solver(v, e, 2, device=-1, face_bc=fb, eps=np.full(K, 2.0))
+    bad = fb.copy()
+    bad[bad == 2] = 3
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, e, 2, device=-1, face_bc=bad)
+    interior = np.zeros((K, 4), dtype=np.int8)
+    m = Mm.Mesh(v, e, R.ref_element(2))
+    k, f = np.argwhere(~m.boundary)[0]
+    interior[k, f] = 2
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, e, 2, device=-1, face_bc=interior)
+    # the material record enlarges the workspace
+    assert P.setup_query(v, e, 3, "f32", eps=np.full(K, 2.0)) > P.setup_query(v, e, 3, "f32")
