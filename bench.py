@@ -42,11 +42,12 @@ def flops_per_elem_stage(N):
     return 36 * Np * Np + 66 * Np + 48 * Np * Nfp + 6 * Np + 58 * 4 * Nfp + 30 * Np
 
 
-def bytes_per_elem_stage(N, word):
+def bytes_per_elem_stage(N, word, material=False):
     """Compulsory HBM bytes of one fused stage per element: read u and res, write u_out and
-    res (24 Np words), the geometric record (9 + 16 words) and four face records (16 B)."""
+    res (24 Np words), the geometric record (9 + 16 words) and four face records (16 B); in a
+    heterogeneous medium also the 20-word material record."""
     Np, _ = counts(N)
-    return 24 * Np * word + 25 * word + 16
+    return 24 * Np * word + 25 * word + 16 + (20 * word if material else 0)
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0901_1024_amd", "csrc", "kernels.hip")
@@ -106,6 +107,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=26)
+    ap.add_argument("--material", action="store_true",
+                    help="heterogeneous medium (eps, mu log-uniform in [1, 4]) with absorbing z = 1 faces")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scales FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -136,7 +139,11 @@ def main():
     word = 4 if prec == "f32" else 8
     t_setup = time.perf_counter()
     v, e = dginputs.kuhn_cube(n, jitter=0.15, permute=True)
-    s = P.Solver(v, e, N, prec, reorder=1, device=0)
+    kw = {}
+    if args.material:
+        eps, mu = dginputs.random_materials(e.shape[0])
+        kw = dict(eps=eps, mu=mu, face_bc=dginputs.faces_on_plane(v, e, 2, 1.0) * 2)
+    s = P.Solver(v, e, N, prec, reorder=1, device=0, **kw)
     x = s.nodes()
     u0 = dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), x[0], x[1], x[2])
     del x
@@ -171,7 +178,7 @@ def main():
     sec = ms / 1e3
     per_launch_s = sec / launches
     flops_launch = K * flops_per_elem_stage(N)
-    bytes_launch = K * bytes_per_elem_stage(N, word)
+    bytes_launch = K * bytes_per_elem_stage(N, word, args.material)
     gflops = flops_launch * launches / sec / 1e9
     gbs = bytes_launch / per_launch_s / 1e9
     tflops_k = flops_launch / per_launch_s / 1e12
@@ -183,8 +190,9 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": round(tflops_k, 2), "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": round(tflops_k / PEAKS_TFLOPS[prec], 4)}
-    roof["traffic"] = recorded_traffic(N, prec, K)
-    roof["kernel"] = (f"mfma_stage_kernel<{N},true>" if prec == "f32" and N in (3, 4)
+    roof["traffic"] = None if args.material else recorded_traffic(N, prec, K)
+    roof["kernel"] = (f"mfma_stage_kernel<{N},true,{'true' if args.material else 'false'}>"
+                      if prec == "f32" and N in (3, 4)
                       else f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>")
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
@@ -205,7 +213,10 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": f"nodal DG Maxwell LSRK4, unit cube 6*{n}^3={K} jittered+permuted tets, "
-                               f"N={N}, {prec}, PEC walls, random smooth fields",
+                               f"N={N}, {prec}, "
+                               + ("random eps/mu in [1,4], absorbing z=1 faces, other walls PEC"
+                                  if args.material else "vacuum, PEC walls")
+                               + ", random smooth fields",
                    "order": N, "K": K, "Np": Np, "stages_per_step": 5, "parallelism": "single GPU"},
         "hbm_gbs": round(gbs, 1),
         "dof_rhs_per_s": round(6 * Np * K * launches / sec, 1),

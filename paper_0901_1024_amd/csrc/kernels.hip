@@ -337,13 +337,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     floatx4 rs4[CPT];
 
-    // ---- face fluxes: fetch every neighbour trace first, then compute
+    // ---- face fluxes: fetch every neighbour trace first, then compute. In the material
+    // variant the face-node slot of this thread is made opaque per tile so that its index
+    // arithmetic is recomputed rather than hoisted out of the tile loop and spilled.
+    int tq = tid;
+    if (MAT) asm volatile("" : "+v"(tq));
     {
       float up[FIT][6];
       floatx4 wm[FIT];   // MAT: face weights A B C D
 #pragma unroll
       for (int r = 0; r < FIT; ++r) {
-        const int q = tid + r * kThreads;
+        const int q = tq + r * kThreads;
         if (q < nel * NF4) {
           const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
           if (MAT)
@@ -384,7 +388,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
 #pragma unroll
       for (int r = 0; r < FIT; ++r) {
-        const int q = tid + r * kThreads;
+        const int q = tq + r * kThreads;
         if (q < nel * NF4) {
           const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
           const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
