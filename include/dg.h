@@ -145,6 +145,35 @@ int dg_energy(const dg_handle* h, double* energy, void* stream);
  * divided by N^2 (host-only). It assumes wave speed at most 1, i.e. eps * mu >= 1. */
 int dg_stable_dt(const dg_handle* h, double cfl, double* dt);
 
+/* ---- Batched form: many meshes of one order and precision in one handle -------------------
+ * The meshes are concatenated (canonical elements of mesh i are [first[i], first[i+1]) of the
+ * handle's canonical arrays); the locality order keeps each mesh contiguous, so one launch per
+ * RK stage advances all of them, and dg_solve replays them from one captured graph. Each mesh
+ * may have its own time step (dg_set_batch_dt): the right-hand side is linear in the
+ * per-element inverse-map derivatives, Fscale and flux weights, so the RK stages read a copy
+ * of those records scaled by the mesh's step and the dt argument of dg_rk_step / dg_solve
+ * multiplies the per-mesh steps (pass 1.0). dg_rhs, dg_energy and the field calls see the
+ * unscaled operator. Meshes may differ in K, geometry, face conditions and materials. */
+
+/* Workspace bytes for dg_setup_batch with the same arguments. */
+int dg_setup_query_batch(const dg_mesh* meshes, int32_t count, const dg_opts* opts,
+                         size_t* workspace_bytes);
+
+/* Like dg_setup for `count` meshes (count >= 1, total K < 2^26). */
+int dg_setup_batch(const dg_mesh* meshes, int32_t count, const dg_opts* opts, void* dev_workspace,
+                   size_t workspace_bytes, void* stream, dg_handle** out);
+
+/* Number of meshes (1 for a plain handle) and, if `first` is not NULL, the count + 1 canonical
+ * element offsets (host array). */
+int dg_batch_info(const dg_handle* h, int32_t* count, int32_t* first);
+
+/* dg_stable_dt of every mesh of the handle, `dt` holds count values (host-only). */
+int dg_batch_stable_dt(const dg_handle* h, double cfl, double* dt);
+
+/* Per-mesh time steps (count finite positive values, host array) for the RK stages of a batch
+ * handle; the default is 1. Uploads the scaled records and synchronises `stream`. */
+int dg_set_batch_dt(dg_handle* h, const double* dt, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,8 @@ _ERRS = {-1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_UNSUPPORTED", -4: "DG_E_OOM"
 # every symbol declared in include/dg.h
 EXPORTS = ["dg_setup_query", "dg_setup", "dg_free", "dg_last_error", "dg_info", "dg_nodes",
            "dg_get_maps", "dg_get_operators", "dg_set_fields", "dg_get_fields", "dg_rhs",
-           "dg_rk_step", "dg_solve", "dg_energy", "dg_stable_dt"]
+           "dg_rk_step", "dg_solve", "dg_energy", "dg_stable_dt", "dg_setup_query_batch",
+           "dg_setup_batch", "dg_batch_info", "dg_batch_stable_dt", "dg_set_batch_dt"]
 
 
 class DGError(RuntimeError):
@@ -82,6 +83,13 @@ def lib():
         L.dg_solve.argtypes = [vp, dbl, i64, vp]
         L.dg_energy.argtypes = [vp, ctypes.POINTER(dbl), vp]
         L.dg_stable_dt.argtypes = [vp, dbl, ctypes.POINTER(dbl)]
+        L.dg_setup_query_batch.argtypes = [ctypes.POINTER(_Mesh), i32, ctypes.POINTER(_Opts),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.dg_setup_batch.argtypes = [ctypes.POINTER(_Mesh), i32, ctypes.POINTER(_Opts), vp, ctypes.c_size_t, vp,
+                                     ctypes.POINTER(vp)]
+        L.dg_batch_info.argtypes = [vp, ctypes.POINTER(i32), vp]
+        L.dg_batch_stable_dt.argtypes = [vp, dbl, vp]
+        L.dg_set_batch_dt.argtypes = [vp, vp, vp]
         for name in EXPORTS:
             if name != "dg_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -157,26 +165,32 @@ class Solver:
     def __init__(self, vxyz, etov, order, precision="f64", reorder=1, device=0, face_bc=None,
                  stream=None, eps=None, mu=None):
         L = lib()
+        m, keep = _mesh_struct(vxyz, etov, face_bc, eps, mu)
+        self._create(order, precision, reorder, device, stream,
+                     lambda o, n: L.dg_setup_query(ctypes.byref(m), ctypes.byref(o), n),
+                     lambda o, ws, n, s, h: L.dg_setup(ctypes.byref(m), ctypes.byref(o), ws, n, s, h))
+        del keep
+
+    def _create(self, order, precision, reorder, device, stream, query, setup):
+        L = lib()
         self.order = order
         self.precision = precision
         self.device = device
-        m, keep = _mesh_struct(vxyz, etov, face_bc, eps, mu)
         o = _opts_struct(order, precision, reorder, device)
         h = ctypes.c_void_p()
         self._ws = None
         if device >= 0:
             import torch
             n = ctypes.c_size_t()
-            _check(L.dg_setup_query(ctypes.byref(m), ctypes.byref(o), ctypes.byref(n)))
+            _check(query(o, ctypes.byref(n)))
             with torch.cuda.device(device):
                 self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=f"cuda:{device}")
                 base = self._ws.data_ptr()
                 aligned = (base + 255) & ~255
-                _check(L.dg_setup(ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(aligned),
-                                  ctypes.c_size_t(n.value), _stream_ptr(stream), ctypes.byref(h)))
+                _check(setup(o, ctypes.c_void_p(aligned), ctypes.c_size_t(n.value), _stream_ptr(stream),
+                             ctypes.byref(h)))
         else:
-            _check(L.dg_setup(ctypes.byref(m), ctypes.byref(o), None, 0, None, ctypes.byref(h)))
-        del keep
+            _check(setup(o, None, 0, None, ctypes.byref(h)))
         self._h = h
         info = _Info()
         _check(L.dg_info(h, ctypes.byref(info)))
@@ -268,3 +282,46 @@ class Solver:
         want = torch.float64 if self.dtype == np.float64 else torch.float32
         if not (t.is_cuda and t.dtype == want and t.is_contiguous() and t.numel() == 6 * self.K * self.Np):
             raise DGError(-1, "expected a contiguous CUDA tensor of 6*K*Np values of the working dtype")
+
+
+class BatchSolver(Solver):
+    """Many meshes of one order and precision in one handle (the batched form).
+
+    meshes: list of dicts with keys vxyz, etov and optionally face_bc, eps, mu. Canonical field
+    arrays are the meshes' arrays concatenated along the element axis; mesh i owns elements
+    first[i]:first[i+1]. Each mesh advances with its own step (set_dts); solve(1.0, n) then
+    takes n steps of every mesh.
+    """
+
+    def __init__(self, meshes, order, precision="f64", reorder=1, device=0, stream=None):
+        L = lib()
+        arr = (_Mesh * len(meshes))()
+        keep = []
+        for i, md in enumerate(meshes):
+            m, k = _mesh_struct(md["vxyz"], md["etov"], md.get("face_bc"), md.get("eps"), md.get("mu"))
+            arr[i] = m
+            keep.append(k)
+        cnt = len(meshes)
+        self._create(order, precision, reorder, device, stream,
+                     lambda o, n: L.dg_setup_query_batch(arr, cnt, ctypes.byref(o), n),
+                     lambda o, ws, n, s, h: L.dg_setup_batch(arr, cnt, ctypes.byref(o), ws, n, s, h))
+        del keep
+        c = ctypes.c_int32()
+        _check(L.dg_batch_info(self._h, ctypes.byref(c), None))
+        self.first = np.empty(c.value + 1, dtype=np.int32)
+        _check(L.dg_batch_info(self._h, ctypes.byref(c), self.first.ctypes.data_as(ctypes.c_void_p)))
+        self.count = c.value
+
+    def stable_dts(self, cfl=0.5):
+        out = np.empty(self.count)
+        _check(lib().dg_batch_stable_dt(self._h, float(cfl), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_dts(self, dts, stream=None):
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        if d.shape != (self.count,):
+            raise DGError(DG_E_ARG, "one time step per mesh")
+        _check(lib().dg_set_batch_dt(self._h, d.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+
+    def mesh_slice(self, i):
+        return slice(int(self.first[i]), int(self.first[i + 1]))

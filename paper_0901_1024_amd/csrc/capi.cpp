@@ -35,8 +35,8 @@ constexpr double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 /
 struct Layout {
   size_t state = 0;  // bytes of one [K][6][Np] array
   size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
-      off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, total;
-  size_t opcat_bytes = 0, mat_bytes = 0;
+      off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, off_geo_dt, off_mat_dt, total;
+  size_t opcat_bytes = 0, mat_bytes = 0, geo_dt_bytes = 0, mat_dt_bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -44,7 +44,9 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // The fragment-ordered concatenated operator is used by the FP32 contraction kernels only.
 int opfrag_words_for(int N, size_t ts) { return (ts == 4 && dgk::mfma_order(N)) ? dgk::opcat_words(N) : 0; }
 
-Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material) {
+// batch: a second copy of the geometric (and material) records scaled by each mesh's time
+// step, read by the RK stages (the right-hand side is linear in them).
+Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool batch = false) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -69,6 +71,10 @@ Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material) {
   L.off_opcat = take(L.opcat_bytes);
   L.mat_bytes = material ? size_t(K) * dgh::kMatStride * ts : 0;
   L.off_mat = take(L.mat_bytes);
+  L.geo_dt_bytes = batch ? size_t(K) * dgh::kGeoStride * ts : 0;
+  L.off_geo_dt = take(L.geo_dt_bytes);
+  L.mat_dt_bytes = batch ? L.mat_bytes : 0;
+  L.off_mat_dt = take(L.mat_dt_bytes);
   L.total = o;
   return L;
 }
@@ -90,6 +96,11 @@ struct dg_handle {
   dgh::RefOps ref;
   dgh::MeshData mesh;
   std::vector<double> mat;   // material records (internal order); empty in vacuum
+  // batch of meshes: canonical element ranges [mesh_first[i], mesh_first[i+1]), the mesh of
+  // each user element, and the unscaled geometric records in internal order
+  bool batch = false;
+  std::vector<int32_t> mesh_first, mesh_of;
+  std::vector<double> geo_int;
   int N = 0, Np = 0, Nfp = 0, K = 0, prec = 0, device = -1;
   size_t ts = 8;
   Layout lay;
@@ -191,6 +202,12 @@ int upload(dg_handle* h, hipStream_t s) {
     mat_b = to_prec(h->mat, h->f64());
     HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_mat), mat_b.data(), mat_b.size(), hipMemcpyHostToDevice, s));
   }
+  if (h->batch) {   // time-step-scaled copies start at dt = 1
+    h->geo_int = geo;
+    HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_geo_dt), geo_b.data(), geo_b.size(), hipMemcpyHostToDevice, s));
+    if (h->lay.mat_dt_bytes)
+      HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_mat_dt), mat_b.data(), mat_b.size(), hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_ops), ops_b.data(), ops_b.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_fcode), M.face_code.data(), M.face_code.size() * 4,
                          hipMemcpyHostToDevice, s));
@@ -223,9 +240,10 @@ int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, 
   args.u_in = in;
   args.out = out;
   args.res = h->at(h->lay.off_res);
-  args.geo = h->at(h->lay.off_geo);
+  const bool scaled = stage && h->batch;   // RK stages of a batch: per-mesh dt in the records
+  args.geo = h->at(scaled ? h->lay.off_geo_dt : h->lay.off_geo);
   args.fcode = static_cast<const int32_t*>(h->at(h->lay.off_fcode));
-  args.mat = h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr;
+  args.mat = h->lay.mat_bytes ? h->at(scaled ? h->lay.off_mat_dt : h->lay.off_mat) : nullptr;
   args.K = h->K;
   args.a = a;
   args.b = b;
@@ -240,6 +258,72 @@ int rk_step_launch(dg_handle* h, double dt, hipStream_t s) {
     if (rc) return rc;
     h->cur ^= 1;
   }
+  return DG_OK;
+}
+
+int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32_t>* mesh_of,
+               const std::vector<int32_t>* mesh_first, void* dev_workspace, size_t workspace_bytes,
+               void* stream, dg_handle** out);
+
+// The meshes of a batch as one mesh: vertex ids offset, elements and their face conditions
+// and materials concatenated in mesh order.
+struct Concat {
+  std::vector<double> vxyz, eps, mu;
+  std::vector<int32_t> etov, mesh_of, first;
+  std::vector<int8_t> bc;
+  dg_mesh m{};
+};
+
+int concat_meshes(const dg_mesh* meshes, int32_t count, Concat& c) {
+  if (!meshes || count < 1) return fail(DG_E_ARG, "a batch needs at least one mesh");
+  int64_t nv = 0, K = 0;
+  bool any_bc = false, any_mat = false;
+  for (int32_t i = 0; i < count; ++i) {
+    const dg_mesh& m = meshes[i];
+    if (!m.vxyz || !m.etov || m.K <= 0 || m.nverts < 4) return fail(DG_E_ARG, "empty or NULL mesh in the batch");
+    nv += m.nverts;
+    K += m.K;
+    any_bc = any_bc || m.face_bc;
+    any_mat = any_mat || m.eps || m.mu;
+  }
+  if (K >= (int64_t(1) << 26) || nv >= (int64_t(1) << 31)) return fail(DG_E_ARG, "batch too large");
+  try {
+    c.vxyz.reserve(size_t(nv) * 3);
+    c.etov.reserve(size_t(K) * 4);
+    c.first.push_back(0);
+    int32_t vbase = 0;
+    for (int32_t i = 0; i < count; ++i) {
+      const dg_mesh& m = meshes[i];
+      c.vxyz.insert(c.vxyz.end(), m.vxyz, m.vxyz + size_t(m.nverts) * 3);
+      for (int64_t q = 0; q < int64_t(m.K) * 4; ++q) {
+        const int32_t v = m.etov[q];
+        if (v < 0 || v >= m.nverts) return fail(DG_E_MESH, "vertex id out of range");
+        c.etov.push_back(v + vbase);
+      }
+      if (any_bc) {
+        if (m.face_bc) c.bc.insert(c.bc.end(), m.face_bc, m.face_bc + size_t(m.K) * 4);
+        else c.bc.insert(c.bc.end(), size_t(m.K) * 4, int8_t(0));
+      }
+      if (any_mat) {
+        for (int k = 0; k < m.K; ++k) {
+          c.eps.push_back(m.eps ? m.eps[k] : 1.0);
+          c.mu.push_back(m.mu ? m.mu[k] : 1.0);
+        }
+      }
+      c.mesh_of.insert(c.mesh_of.end(), size_t(m.K), i);
+      c.first.push_back(c.first.back() + m.K);
+      vbase += m.nverts;
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(DG_E_OOM, "host allocation failed");
+  }
+  c.m.nverts = int32_t(nv);
+  c.m.vxyz = c.vxyz.data();
+  c.m.K = int32_t(K);
+  c.m.etov = c.etov.data();
+  c.m.face_bc = any_bc ? c.bc.data() : nullptr;
+  c.m.eps = any_mat ? c.eps.data() : nullptr;
+  c.m.mu = any_mat ? c.mu.data() : nullptr;
   return DG_OK;
 }
 
@@ -262,16 +346,33 @@ int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_b
 
 int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size_t workspace_bytes,
              void* stream, dg_handle** out) {
+  return setup_impl(mesh, opts, nullptr, nullptr, dev_workspace, workspace_bytes, stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// mesh_of (K or null): mesh id of each element of a concatenated batch; mesh_first: canonical
+// element offsets of the meshes (count + 1 entries).
+int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32_t>* mesh_of,
+               const std::vector<int32_t>* mesh_first, void* dev_workspace, size_t workspace_bytes,
+               void* stream, dg_handle** out) {
   if (out) *out = nullptr;
   if (!out) return fail(DG_E_ARG, "out must not be NULL");
   int rc = check_inputs(mesh, opts);
   if (rc) return rc;
   std::unique_ptr<dg_handle> h(new (std::nothrow) dg_handle);
   if (!h) return fail(DG_E_OOM, "host allocation failed");
+  if (mesh_of) {
+    h->batch = true;
+    h->mesh_of = *mesh_of;
+    h->mesh_first = *mesh_first;
+  }
   try {
     h->ref = dgh::build_ref_ops(opts->order);
     h->mesh = dgh::build_mesh(h->ref, mesh->nverts, mesh->vxyz, mesh->K, mesh->etov, mesh->face_bc,
-                              opts->reorder);
+                              opts->reorder, mesh_of ? mesh_of->data() : nullptr);
   } catch (const std::bad_alloc&) {
     return fail(DG_E_OOM, "host allocation failed");
   } catch (const std::exception& ex) {
@@ -293,7 +394,7 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
   h->prec = opts->precision;
   h->ts = h->f64() ? 8 : 4;
   h->device = opts->device;
-  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty());
+  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty(), h->batch);
   if (h->device >= 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());
@@ -324,6 +425,10 @@ int dg_setup(const dg_mesh* mesh, const dg_opts* opts, void* dev_workspace, size
   *out = h.release();
   return DG_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int dg_free(dg_handle* h) {
   if (!h) return DG_OK;
@@ -501,6 +606,88 @@ int dg_stable_dt(const dg_handle* h, double cfl, double* dt) {
     for (int f = 0; f < 4; ++f)
       mn = std::min(mn, 1.0 / h->mesh.geo[size_t(k) * dgh::kGeoStride + dgh::kGeoNormal + 4 * f + 3]);
   *dt = cfl * mn / (double(h->N) * h->N);
+  return DG_OK;
+}
+
+int dg_setup_query_batch(const dg_mesh* meshes, int32_t count, const dg_opts* opts, size_t* workspace_bytes) {
+  Concat c;
+  int rc = concat_meshes(meshes, count, c);
+  if (rc) return rc;
+  rc = check_inputs(&c.m, opts);
+  if (rc) return rc;
+  if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
+  const int N = opts->order;
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  *workspace_bytes = make_layout(c.m.K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4,
+                                 c.m.eps != nullptr, true).total;
+  return DG_OK;
+}
+
+int dg_setup_batch(const dg_mesh* meshes, int32_t count, const dg_opts* opts, void* dev_workspace,
+                   size_t workspace_bytes, void* stream, dg_handle** out) {
+  if (out) *out = nullptr;
+  Concat c;
+  int rc = concat_meshes(meshes, count, c);
+  if (rc) return rc;
+  return setup_impl(&c.m, opts, &c.mesh_of, &c.first, dev_workspace, workspace_bytes, stream, out);
+}
+
+int dg_batch_info(const dg_handle* h, int32_t* count, int32_t* first) {
+  if (!h || !count) return fail(DG_E_ARG, "NULL argument");
+  if (!h->batch) {
+    *count = 1;
+    if (first) first[0] = 0, first[1] = h->K;
+    return DG_OK;
+  }
+  *count = int32_t(h->mesh_first.size()) - 1;
+  if (first) std::copy(h->mesh_first.begin(), h->mesh_first.end(), first);
+  return DG_OK;
+}
+
+int dg_batch_stable_dt(const dg_handle* h, double cfl, double* dt) {
+  if (!h || !dt) return fail(DG_E_ARG, "NULL argument");
+  const int count = h->batch ? int(h->mesh_first.size()) - 1 : 1;
+  for (int i = 0; i < count; ++i) dt[i] = 1e300;
+  for (int k = 0; k < h->K; ++k) {
+    const int i = h->batch ? h->mesh_of[k] : 0;
+    for (int f = 0; f < 4; ++f)
+      dt[i] = std::min(dt[i], 1.0 / h->mesh.geo[size_t(k) * dgh::kGeoStride + dgh::kGeoNormal + 4 * f + 3]);
+  }
+  for (int i = 0; i < count; ++i) dt[i] *= cfl / (double(h->N) * h->N);
+  return DG_OK;
+}
+
+int dg_set_batch_dt(dg_handle* h, const double* dt, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!h->batch) return fail(DG_E_ARG, "not a batch handle");
+  if (!dt) return fail(DG_E_ARG, "NULL dt");
+  const int count = int(h->mesh_first.size()) - 1;
+  for (int i = 0; i < count; ++i)
+    if (!(std::isfinite(dt[i]) && dt[i] > 0.0)) return fail(DG_E_ARG, "time steps must be finite and positive");
+  rc = set_device(h);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // scale the inverse-map derivatives and Fscale (the right-hand side is linear in them) and
+  // the material face weights; normals, J and the material constants stay
+  const int K = h->K;
+  std::vector<double> geo(h->geo_int), mat(h->mat);
+  for (int i = 0; i < K; ++i) {
+    const double sc = dt[h->mesh_of[h->mesh.elem_of[i]]];
+    double* g = &geo[size_t(i) * dgh::kGeoStride];
+    for (int q = 0; q < 9; ++q) g[q] *= sc;
+    for (int f = 0; f < 4; ++f) g[dgh::kGeoNormal + 4 * f + 3] *= sc;
+    if (!mat.empty())
+      for (int q = dgh::kMatFace; q < dgh::kMatStride; ++q) mat[size_t(i) * dgh::kMatStride + q] *= sc;
+  }
+  std::vector<char> geo_b = to_prec(geo, h->f64());
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_geo_dt), geo_b.data(), geo_b.size(), hipMemcpyHostToDevice, s));
+  std::vector<char> mat_b;
+  if (h->lay.mat_dt_bytes) {
+    mat_b = to_prec(mat, h->f64());
+    HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_mat_dt), mat_b.data(), mat_b.size(), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));   // host staging buffers die at return
   return DG_OK;
 }
 

@@ -24,7 +24,7 @@ uint64_t spread3(uint64_t v) {
 }  // namespace
 
 MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, const int32_t* etov_in,
-                    const int8_t* face_bc, int reorder) {
+                    const int8_t* face_bc, int reorder, const int32_t* group) {
   if (K <= 0 || nverts < 4) throw std::runtime_error("empty mesh");
   if (K >= (1 << 26)) throw std::runtime_error("too many elements for the packed face record");
   MeshData m;
@@ -200,8 +200,12 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
       }
       code[k] = c;
     }
-    std::stable_sort(m.elem_of.begin(), m.elem_of.end(),
-                     [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    // with groups (the meshes of a batch) the order is by group first, so that each group
+    // stays contiguous and its tiles hold only its own elements' neighbours
+    std::stable_sort(m.elem_of.begin(), m.elem_of.end(), [&](int32_t a, int32_t b) {
+      if (group && group[a] != group[b]) return group[a] < group[b];
+      return code[a] < code[b];
+    });
   } else if (reorder != 0) {
     throw std::runtime_error("unknown reorder mode");
   }

@@ -60,9 +60,10 @@ struct MeshData {
 
 // Throws std::runtime_error with a message on an invalid mesh (degenerate element, a face
 // shared by more than two elements, bad vertex id). face_bc (K x 4 or null) is indexed by the
-// faces of etov as given: 0 automatic (wall if unmatched), 1 wall, 2 absorbing.
+// faces of etov as given: 0 automatic (wall if unmatched), 1 wall, 2 absorbing. group (K or
+// null): elements of one group stay contiguous, in group order, under the locality order.
 MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, const int32_t* etov,
-                    const int8_t* face_bc, int reorder);
+                    const int8_t* face_bc, int reorder, const int32_t* group = nullptr);
 
 // Material records (K x kMatStride, internal order) for per-element eps, mu (user order; a
 // null array means 1). Throws on a value that is not finite and positive.

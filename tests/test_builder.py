@@ -121,3 +121,37 @@ def test_material_and_face_condition_errors():
         P.Solver(v, e, 2, device=-1, face_bc=interior)
     # the material record enlarges the workspace
     assert P.setup_query(v, e, 3, "f32", eps=np.full(K, 2.0)) > P.setup_query(v, e, 3, "f32")
+
+
+def _batch_meshes():
+    out = []
+    for i, (n, jit) in enumerate([(1, 0.0), (2, 0.15), (2, 0.1)]):
+        v, e = dginputs.kuhn_cube(n, jitter=jit, permute=True)
+        md = {"vxyz": v, "etov": e}
+        if i == 2:
+            md["eps"], md["mu"] = dginputs.random_materials(e.shape[0])
+            md["face_bc"] = dginputs.faces_on_plane(v, e, 2, 1.0) * 2
+        out.append(md)
+    return out
+
+
+def test_batch_is_the_concatenation_of_its_meshes():
+    meshes = _batch_meshes()
+    b = P.BatchSolver(meshes, 2, device=-1)
+    assert b.count == 3
+    Ks = [md["etov"].shape[0] for md in meshes]
+    assert list(b.first) == [0, Ks[0], Ks[0] + Ks[1], sum(Ks)]
+    vM, vP = b.get_maps()
+    x = b.nodes()
+    dts = b.stable_dts(0.5)
+    for i, md in enumerate(meshes):
+        s = P.Solver(md["vxyz"], md["etov"], 2, device=-1, face_bc=md.get("face_bc"),
+                     eps=md.get("eps"), mu=md.get("mu"))
+        sl = b.mesh_slice(i)
+        m1, p1 = s.get_maps()
+        off = int(b.first[i]) * s.Np
+        assert np.array_equal(vM[sl], m1 + off) and np.array_equal(vP[sl], p1 + off)
+        assert np.array_equal(x[:, sl], s.nodes())
+        assert dts[i] == s.stable_dt(0.5)
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        P.BatchSolver([], 2, device=-1)
