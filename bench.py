@@ -97,6 +97,82 @@ def cpu_baseline(N, n_sample):
             "seconds": sec}
 
 
+def run_batch(args):
+    """Batched form: 64 independent jittered cube meshes (K log-uniform in [1e3, 5e4], N uniform
+    in 2..6, FP32, seed 4), each advanced `batch_steps` steps with its own stable step. Plain:
+    one handle per mesh, dg_solve mesh after mesh on one stream. Batched: one handle per order
+    (all meshes of that order concatenated), dg_solve of each. Both start from the same fields,
+    take two untimed warm-up steps, and must end within the FP32 parity tolerance."""
+    import numpy as np
+    import torch
+
+    import dginputs
+    import paper_0901_1024_amd as P
+
+    specs = dginputs.batch_specs()
+    meshes = []
+    for i, sp in enumerate(specs):
+        v, e = dginputs.kuhn_cube(0, jitter=0.15, permute=True, seed_jitter=100 + i, seed_perm=200 + i,
+                                  nx=sp["nx"], ny=sp["ny"], nz=sp["nz"])
+        meshes.append({"vxyz": v, "etov": e, "order": sp["order"]})
+    steps, prec = args.batch_steps, "f32"
+    plain = [P.Solver(md["vxyz"], md["etov"], md["order"], prec) for md in meshes]
+    u0 = [dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), *s.nodes()) for s in plain]
+    dts = [s.stable_dt(0.5) for s in plain]
+    orders = sorted({md["order"] for md in meshes})
+    groups = {N: [i for i, md in enumerate(meshes) if md["order"] == N] for N in orders}
+    batched = {}
+    for N, idx in groups.items():
+        b = P.BatchSolver([meshes[i] for i in idx], N, prec)
+        b.set_dts(b.stable_dts(0.5))
+        b.set_fields(np.concatenate([u0[i] for i in idx], axis=1))
+        batched[N] = b
+    for i, s in enumerate(plain):
+        s.set_fields(u0[i])
+    stream = torch.cuda.current_stream()
+
+    def timed(run):
+        run(2)
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run(steps)
+        z.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / 1e3
+
+    t_plain = timed(lambda n: [s.solve(dts[i], n) for i, s in enumerate(plain)])
+    t_batch = timed(lambda n: [b.solve(1.0, n) for b in batched.values()])
+    worst = 0.0
+    for N, idx in groups.items():
+        got = batched[N].get_fields()
+        for j, i in enumerate(idx):
+            ref = plain[i].get_fields()
+            sl = batched[N].mesh_slice(j)
+            worst = max(worst, float(np.linalg.norm(got[:, sl] - ref) / np.linalg.norm(ref)))
+    if not worst <= 1e-5:
+        print(f"batched and plain results differ: {worst:.2e}", file=sys.stderr)
+        sys.exit(1)
+    Ks = [md["etov"].shape[0] for md in meshes]
+    flops = sum(5 * steps * K * flops_per_elem_stage(md["order"]) for K, md in zip(Ks, meshes))
+    out = {
+        "metric": "solves/s, batched (one handle per order) vs plain per-mesh loop",
+        "value": round(len(meshes) / t_batch, 3), "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": 2, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"64 jittered+permuted cube meshes, K log-uniform in [1e3, 5e4] "
+                               f"(total {sum(Ks)}), N uniform in 2..6, FP32, {steps} steps each at "
+                               f"its own stable step",
+                   "meshes": len(meshes), "K_total": sum(Ks), "orders": {str(N): len(v) for N, v in groups.items()}},
+        "plain_solves_per_s": round(len(meshes) / t_plain, 3),
+        "speedup_batched_over_plain": round(t_plain / t_batch, 3),
+        "batched_gflops": round(flops / t_batch / 1e9, 1), "plain_gflops": round(flops / t_plain / 1e9, 1),
+        "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4)},
+        "max_rel_diff_batched_vs_plain": worst,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +183,9 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=26)
+    ap.add_argument("--batch", action="store_true",
+                    help="batched form: 64 meshes of mixed size and order, batched vs plain loop")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--material", action="store_true",
                     help="heterogeneous medium (eps, mu log-uniform in [1, 4]) with absorbing z = 1 faces")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -121,6 +200,9 @@ def main():
     import numpy as np
     import torch
 
+    if args.batch:
+        run_batch(args)
+        return
     if args.copy_calibration:
         n = 256 * 1024 * 1024 // 4
         a = torch.ones(n, device="cuda")
