@@ -273,8 +273,9 @@ def main():
         roof = {"bound": "mfma", "achieved": round(tflops_k, 2), "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": round(tflops_k / PEAKS_TFLOPS[prec], 4)}
     roof["traffic"] = None if args.material else recorded_traffic(N, prec, K)
-    roof["kernel"] = (f"mfma_stage_kernel<{N},true,{'true' if args.material else 'false'}>"
-                      if prec == "f32" and N in (3, 4)
+    mat = "true" if args.material else "false"
+    roof["kernel"] = (f"mfma_stage_kernel<{N},true,{mat}>" if prec == "f32" and N in (3, 4)
+                      else f"hmfma_stage_kernel<{N},true,{mat}>" if prec == "f32" and N in (5, 6)
                       else f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>")
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)

@@ -624,16 +624,391 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// MFMA form of the fused stage for the higher orders (FP32, N = 5, 6).
+//
+// The same contraction as above (contravariant fluxes; rhs = OpCat x [G; Fscale/2 flux]; the
+// k-steps in volume quads, face quads and volume singles, each lane reading four k-steps with
+// one 16-byte LDS read) with the sizes of the higher orders in mind: the operator is too large
+// to copy into LDS per workgroup (NT x KS x 256 B = 67 KB at N = 5), so each wave owns one
+// 16-node column tile and keeps that tile's operator fragments in VGPRs for the life of the
+// persistent workgroup (KS = 66 / 91 per lane). A tile holds 8 elements (48 rows = 3 row
+// tiles, all handled by every wave); the last column tile is zero-padded (operator rows >= Np
+// are zero), which replaces the 4x4x1 tail.
+template <int N>
+struct HDims {
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, Nf4 = Dims<N>::Nf4;
+  static constexpr int E = 8;                         // elements per tile
+  static constexpr int ROWS = 6 * E;                  // (field, element) rows, field-major
+  static constexpr int RT = ROWS / 16;                // row tiles, all owned by every wave
+  static constexpr int NT = (Np + 15) / 16;           // column tiles (last one padded)
+  static constexpr int THREADS = 64 * NT;             // one wave per column tile
+  static constexpr int TW = E * 6 * Np;
+  static constexpr int TW4 = TW / 4;
+  static constexpr int CPT = (TW4 + THREADS - 1) / THREADS;
+  static constexpr int NPP = (Np + 3) / 4 * 4;
+  static constexpr int ES = 6 * NPP + 4;              // = 4 mod 8 (conflict-free rows)
+  static constexpr int NF = (Nf4 + 15) / 16 * 16;
+  static constexpr int RSL = NF + 4;
+  static constexpr int KV = 3 * NPP;
+  static constexpr int KD = KV + NF;
+  static constexpr int KS = KD / 4;
+  static constexpr int VB = NPP / 16;
+  static constexpr int VR = (NPP - 16 * VB) / 4;
+  static constexpr int QV = 3 * VB, QF = NF / 16;
+  static constexpr int NQ = QV + QF;
+  static constexpr int FIT = (E * Nf4 + THREADS - 1) / THREADS;
+  static constexpr int OPC = NT * KS * 64;            // fragment-ordered operator, no tail
+  static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
+  static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
+  static_assert(TW <= ROWS * RSL, "staging must fit in the flux rows");
+  static_assert(ROWS % 16 == 0, "whole row tiles");
+};
+
+template <int N, bool STAGE, bool MAT>
+__global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
+    const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
+    const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
+    const float* __restrict__ opf, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
+  using D = HDims<N>;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
+                NF = D::NF, KS = D::KS, RSL = D::RSL, RT = D::RT, FIT = D::FIT, TW = D::TW,
+                TW4 = D::TW4, CPT = D::CPT, VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF,
+                NQ = D::NQ, NTH = D::THREADS;
+  constexpr int G = dgh::kGeoStride;
+  constexpr int GW = E * G;
+  constexpr int GPT = (GW + NTH - 1) / NTH;
+  __shared__ __align__(16) float us[TW];              // field tile [e][f][n]
+  __shared__ __align__(16) float up_s[E * ES];        // padded copy [e][f][NPP]
+  __shared__ __align__(16) float gl[D::ROWS * RSL];   // flux rows [f E + e][fj]; later staging
+  __shared__ float gt[GW];
+  __shared__ int32_t fc[E * 4];
+  __shared__ uint8_t nbr_s[96 * NFP];
+  __shared__ uint8_t fm_s[4 * NFP];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's column tile
+  const int g4 = lane >> 4, li = lane & 15;
+
+  const int nwg = gridDim.x / kXcds;
+  const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
+  const int TX = (ntiles + kXcds - 1) / kXcds;
+  const int tend = min(ntiles, (xcd + 1) * TX);
+  int tile = xcd * TX + wj;
+  if (tile >= tend) return;
+
+  // once per workgroup: this wave's operator fragments (registers) and the node tables
+  floatx4 bq[NQ];
+  float bs[3 * VR > 0 ? 3 * VR : 1];
+  {
+    const floatx4* src = reinterpret_cast<const floatx4*>(opf + size_t(nt) * KS * 64) + lane;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bq[q] = src[64 * q];
+    const float* s1 = opf + size_t(nt) * KS * 64 + NQ * 256 + lane;
+#pragma unroll
+    for (int q = 0; q < 3 * VR; ++q) bs[q] = s1[64 * q];
+  }
+  for (int q = tid; q < 96 * NFP; q += NTH) nbr_s[q] = uint8_t(nbrnode[q]);
+  for (int q = tid; q < 4 * NFP; q += NTH) fm_s[q] = uint8_t(fmask[q]);
+
+  floatx4 pu[CPT];
+  float pg[GPT];
+  int32_t pf = 0;
+  float pm = 0.f;
+  auto prefetch = [&](int t) __attribute__((always_inline)) {
+    if (t * E + E <= K) {
+      const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NP);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) pu[r] = s4[min(tid + r * NTH, TW4 - 1)];
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * NTH, GW - 1)];
+      pf = fcode[size_t(t) * E * 4 + min(tid, E * 4 - 1)];
+      if (MAT) {
+        const int q = min(tid, 2 * E - 1);
+        pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
+      }
+    }
+  };
+  prefetch(tile);
+
+  for (; tile < tend; tile += nwg) {
+    const int base = tile * E;
+    const int nel = min(E, K - base);
+    const bool full = nel == E;
+    const size_t tb = size_t(base) * 6 * NP;
+
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < TW4) reinterpret_cast<floatx4*>(us)[q] = pu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < GW) gt[q] = pg[r];
+      }
+      if (tid < E * 4) fc[tid] = pf;
+      if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += NTH) us[q] = u_in[tb + q];
+      if (MAT)
+        for (int q = tid; q < 2 * nel; q += NTH)
+          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+      for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
+      for (int q = tid; q < nel * 4; q += NTH) fc[q] = fcode[size_t(base) * 4 + q];
+    }
+    __syncthreads();
+
+    floatx4 rs4[CPT];
+
+    // ---- face fluxes (as in the kernel above)
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+    {
+      float up[FIT][6];
+      floatx4 wm[FIT];
+#pragma unroll
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tq + r * NTH;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          if (MAT)
+            wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
+                                                      dgh::kMatFace + 4 * f);
+          const int code = fc[e * 4 + f];
+          if (code >= 0) {
+            const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
+            const int nn = nbr_s[((f * 4 + f2) * 6 + o) * NFP + j];
+            const int le = nb - base;
+            if (le >= 0 && le < nel) {
+              const float* p = us + le * 6 * NP + nn;
+#pragma unroll
+              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
+            } else {
+              const float* p = u_in + size_t(nb) * 6 * NP + nn;
+#pragma unroll
+              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
+            }
+          }
+        }
+      }
+      for (int q = tid; q < nel * 6 * (NPP / 4); q += NTH) {
+        const int row = q / (NPP / 4), j4 = 4 * (q - row * (NPP / 4));   // row = 6 e + f
+        const float* src = us + row * NP + j4;
+        floatx4 v;
+        v.x = src[0];
+        v.y = j4 + 1 < NP ? src[1] : 0.f;
+        v.z = j4 + 2 < NP ? src[2] : 0.f;
+        v.w = j4 + 3 < NP ? src[3] : 0.f;
+        *reinterpret_cast<floatx4*>(up_s + (row / 6) * ES + (row % 6) * NPP + j4) = v;
+      }
+      for (int q = tid; q < D::ROWS * (NF - NF4); q += NTH) {
+        const int row = q / (NF - NF4);
+        gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tq + r * NTH;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+          const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
+          const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
+          const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
+          float dEx, dEy, dEz, dHx, dHy, dHz;
+          const int code = fc[e * 4 + f];
+          if (code == dgh::kFacePec) {
+            dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
+            dHx = dHy = dHz = 0.f;
+          } else if (code < 0) {
+            dEx = -Ex, dEy = -Ey, dEz = -Ez;
+            dHx = -Hx, dHy = -Hy, dHz = -Hz;
+          } else {
+            dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
+            dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
+          }
+          const float ndE = nx * dEx + ny * dEy + nz * dEz;
+          const float ndH = nx * dHx + ny * dHy + nz * dHz;
+          float* o = gl + e * RSL + fj;
+          if (MAT) {
+            const float A = wm[r].x, B = wm[r].y, C = wm[r].z, Dd = wm[r].w;
+            o[0 * E * RSL] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
+            o[1 * E * RSL] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
+            o[2 * E * RSL] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
+            o[3 * E * RSL] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
+            o[4 * E * RSL] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
+            o[5 * E * RSL] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
+          } else {
+            o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
+            o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
+            o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
+            o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
+            o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
+            o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (STAGE && full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r)
+        rs4[r] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + r * NTH, TW4 - 1)];
+    }
+    if (tile + nwg < tend) prefetch(tile + nwg);
+
+    // ---- contraction: this wave's column tile against the three row tiles. Row tile t holds
+    // rows 16 t + li, row = f E + e (two fields of 8 elements).
+    floatx4 acc[RT];
+    {
+      float pc[RT][3], qc[RT][3];
+      const float* vc[RT];
+      const float* vb[RT];
+      const float* fl[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int row = 16 * t + li;
+        const int f = row / E, e = row - f * E;
+        const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+        const int srcf = f < 3 ? 3 : 0;
+        const float sg = f < 3 ? 1.f : -1.f;
+        const float* cm = gt + e * G;
+        const float sm = MAT ? sg * up_s[e * ES + 6 * NPP + (f < 3 ? 0 : 1)] : sg;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          pc[t][mu] = sm * cm[3 * mu + b];
+          qc[t][mu] = -sm * cm[3 * mu + c];
+        }
+        vc[t] = up_s + e * ES + (srcf + c) * NPP;
+        vb[t] = up_s + e * ES + (srcf + b) * NPP;
+        fl[t] = gl + row * RSL + 4 * g4;
+      }
+#pragma unroll
+      for (int jb = 0; jb < VB; ++jb) {
+        floatx4 xc[RT], xb[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          xc[t] = *reinterpret_cast<const floatx4*>(vc[t] + 16 * jb + 4 * g4);
+          xb[t] = *reinterpret_cast<const floatx4*>(vb[t] + 16 * jb + 4 * g4);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const floatx4 w = bq[3 * jb + mu];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const float ws = s == 0 ? w.x : s == 1 ? w.y : s == 2 ? w.z : w.w;
+            float av[RT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+              const float xcs = s == 0 ? xc[t].x : s == 1 ? xc[t].y : s == 2 ? xc[t].z : xc[t].w;
+              const float xbs = s == 0 ? xb[t].x : s == 1 ? xb[t].y : s == 2 ? xb[t].z : xb[t].w;
+              av[t] = pc[t][mu] * xcs + qc[t][mu] * xbs;
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], ws, acc[t], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int fb = 0; fb < QF; ++fb) {
+        floatx4 xf[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) xf[t] = *reinterpret_cast<const floatx4*>(fl[t] + 16 * fb);
+        const floatx4 w = bq[QV + fb];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float ws = s == 0 ? w.x : s == 1 ? w.y : s == 2 ? w.z : w.w;
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const float xs = s == 0 ? xf[t].x : s == 1 ? xf[t].y : s == 2 ? xf[t].z : xf[t].w;
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs, ws, acc[t], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < VR; ++r) {
+        float xc1[RT], xb1[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          xc1[t] = vc[t][16 * VB + 4 * r + g4];   // columns >= Np read the zero padding
+          xb1[t] = vb[t][16 * VB + 4 * r + g4];
+        }
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const float w = bs[3 * r + mu];
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pc[t][mu] * xc1[t] + qc[t][mu] * xb1[t], w, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();   // flux rows are read: reuse them for the staging
+
+    // ---- stage the right-hand side [e][f][n]: lane (li, g4), register i = row 16 t + 4 g4 + i,
+    // node 16 nt + li (nodes >= Np are the padding of the last column tile)
+    float* stage = gl;
+    const int col = 16 * nt + li;
+    if (col < NP) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * t + 4 * g4 + i;
+          const int f = row / E, e = row - f * E;
+          stage[(e * 6 + f) * NP + col] = acc[t][i];
+        }
+    }
+    __syncthreads();
+
+    // ---- update and write out, coalesced
+    if (full) {
+      floatx4* o4 = reinterpret_cast<floatx4*>(out + tb);
+      floatx4* r4 = reinterpret_cast<floatx4*>(res + tb);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < TW4) {
+          const floatx4 h = reinterpret_cast<const floatx4*>(stage)[q];
+          if (STAGE) {
+            const floatx4 u = reinterpret_cast<const floatx4*>(us)[q];
+            const floatx4 rv = ca * rs4[r] + cdt * h;
+            r4[q] = rv;
+            o4[q] = u + cb * rv;
+          } else {
+            o4[q] = h;
+          }
+        }
+      }
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += NTH) {
+        const float h = stage[q];
+        if (STAGE) {
+          const float rv = ca * res[tb + q] + cdt * h;
+          res[tb + q] = rv;
+          out[tb + q] = us[q] + cb * rv;
+        } else {
+          out[tb + q] = h;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Resident workgroups for the persistent grid: CUs x workgroups per CU, a multiple of the XCD
-// count (queried once per kernel).
-template <typename Kern>
-int persistent_grid(Kern kern, int ntiles) {
+// count (queried once per kernel: the template argument is the kernel itself, so every kernel
+// keeps its own count).
+template <auto Kern>
+int persistent_grid(int threads, int ntiles) {
   static int cached = 0;
   if (!cached) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, 0) != hipSuccess || per < 1)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, Kern, threads, 0) != hipSuccess || per < 1)
       per = 1, cus = 256;
     cached = ((cus * per + kXcds - 1) / kXcds) * kXcds;
   }
@@ -645,13 +1020,32 @@ template <int N, bool STAGE, bool MAT>
 hipError_t launch_mfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = MDims<N>::E;
   const int ntiles = (a.K + E - 1) / E;
-  const int nb = persistent_grid(mfma_stage_kernel<N, STAGE, MAT>, ntiles);
+  const int nb = persistent_grid<mfma_stage_kernel<N, STAGE, MAT>>(kThreads, ntiles);
   mfma_stage_kernel<N, STAGE, MAT><<<nb, kThreads, 0, s>>>(
       static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
       static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
       static_cast<const float*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
       STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f);
   return hipGetLastError();
+}
+
+template <int N, bool STAGE, bool MAT>
+hipError_t launch_hmfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const int E = HDims<N>::E;
+  const int ntiles = (a.K + E - 1) / E;
+  const int nb = persistent_grid<hmfma_stage_kernel<N, STAGE, MAT>>(HDims<N>::THREADS, ntiles);
+  hmfma_stage_kernel<N, STAGE, MAT><<<nb, HDims<N>::THREADS, 0, s>>>(
+      static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
+      static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
+      static_cast<const float*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
+      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_hmfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  if (a.mat) return stage ? launch_hmfma_v<N, true, true>(ops, a, s) : launch_hmfma_v<N, false, true>(ops, a, s);
+  return stage ? launch_hmfma_v<N, true, false>(ops, a, s) : launch_hmfma_v<N, false, false>(ops, a, s);
 }
 
 template <int N>
@@ -791,18 +1185,19 @@ int opcat_words(int N) {
   switch (N) {
     case 3: return MDims<3>::OPC;
     case 4: return MDims<4>::OPC;
+    case 5: return HDims<5>::OPC;
+    case 6: return HDims<6>::OPC;
   }
   return 0;
 }
 
-bool mfma_order(int N) { return N == 3 || N == 4; }
+bool mfma_order(int N) { return N >= 3 && N <= 6; }
 
 namespace {
 // Decodes a column k of the padded concatenation [D_r | D_s | D_t] (NPP columns each) + LIFT
 // (NF columns) into operator block and column within it.
-template <int N>
+template <typename D>
 void opcat_column(int k, int* blk, int* col) {
-  using D = MDims<N>;
   if (k < D::KV) {
     *blk = k / D::NPP;
     *col = k % D::NPP;
@@ -812,9 +1207,8 @@ void opcat_column(int k, int* blk, int* col) {
   }
 }
 
-template <int N>
+template <typename D>
 void opfrag_source_t(int w, int* n, int* blk, int* col) {
-  using D = MDims<N>;
   const int per_tile = D::KS * 64;
   int k = 0;
   if (w < D::NT * per_tile) {
@@ -846,14 +1240,16 @@ void opfrag_source_t(int w, int* n, int* blk, int* col) {
       k = (sg % 3) * D::NPP + 16 * D::VB + 4 * (sg / 3) + g;
     }
   }
-  opcat_column<N>(k, blk, col);
+  opcat_column<D>(k, blk, col);
 }
 }  // namespace
 
 void opfrag_source(int N, int w, int* n, int* blk, int* col) {
   switch (N) {
-    case 3: return opfrag_source_t<3>(w, n, blk, col);
-    case 4: return opfrag_source_t<4>(w, n, blk, col);
+    case 3: return opfrag_source_t<MDims<3>>(w, n, blk, col);
+    case 4: return opfrag_source_t<MDims<4>>(w, n, blk, col);
+    case 5: return opfrag_source_t<HDims<5>>(w, n, blk, col);
+    case 6: return opfrag_source_t<HDims<6>>(w, n, blk, col);
   }
   *n = *blk = *col = -1;
 }
@@ -876,6 +1272,8 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
   if (!f64 && ops.opfrag) {
     if (N == 3) return launch_mfma_t<3>(stage, ops, a, s);
     if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);
+    if (N == 5) return launch_hmfma_t<5>(stage, ops, a, s);
+    if (N == 6) return launch_hmfma_t<6>(stage, ops, a, s);
   }
   return f64 ? dispatch_stage<double>(N, stage, ops, a, s) : dispatch_stage<float>(N, stage, ops, a, s);
 }
