@@ -1,0 +1,71 @@
+"""The serving loop's admission and accounting on the host (a fake device: no GPU)."""
+import numpy as np
+import pytest
+
+from paper_0901_1024_amd.serve import Request, Server, summary
+
+
+class FakeBackend:
+    """Footprint = 100 B per element; a chunk of n steps takes n polls to finish."""
+
+    def __init__(self):
+        self.in_flight = 0
+        self.max_in_flight = 0
+        self.used = 0
+        self.max_used = 0
+
+    def footprint(self, r):
+        return 100 * r.etov.shape[0]
+
+    def setup(self, r):
+        self.in_flight += 1
+        self.used += self.footprint(r)
+        self.max_in_flight = max(self.max_in_flight, self.in_flight)
+        self.max_used = max(self.max_used, self.used)
+        return [r], None, 1.0
+
+    def advance(self, solver, stream, dt, n):
+        return {"polls": n}
+
+    def finished(self, ev):
+        ev["polls"] -= 1
+        return ev["polls"] <= 0
+
+    def fetch(self, solver, stream):
+        return np.zeros(1)
+
+    def release(self, solver):
+        self.in_flight -= 1
+        self.used -= self.footprint(solver[0])
+
+
+def _requests(Ks, arrivals, steps=6):
+    return [Request(rid=i, arrival=a, vxyz=np.zeros((4, 3)), etov=np.zeros((K, 4), dtype=np.int32),
+                    order=3, steps=steps, init=lambda x: x)
+            for i, (K, a) in enumerate(zip(Ks, arrivals))]
+
+
+def test_admission_respects_budget_and_slots():
+    be = FakeBackend()
+    reqs = _requests([10, 20, 30, 40, 50, 60], [0.0] * 6)
+    done = Server(budget_bytes=100 * 70, slots=3, chunk_steps=2, backend=be).run(reqs)
+    assert len(done) == 6 and be.in_flight == 0
+    assert be.max_used <= 100 * 70 and be.max_in_flight <= 3
+    assert all(r.t_done >= r.t_admit >= r.arrival for r in done)
+
+
+def test_one_slot_is_first_in_first_out():
+    be = FakeBackend()
+    reqs = _requests([5, 5, 5, 5], [0.0, 0.0, 0.0, 0.0])
+    done = Server(budget_bytes=10 ** 9, slots=1, chunk_steps=2, backend=be).run(reqs)
+    assert [r.rid for r in done] == [0, 1, 2, 3]
+    assert be.max_in_flight == 1
+    s = summary(done)
+    assert s["completed"] == 4 and s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_oversized_request_is_refused_and_chunks_are_even():
+    with pytest.raises(ValueError):
+        Server(budget_bytes=100, slots=2, backend=FakeBackend()).run(_requests([10], [0.0]))
+    with pytest.raises(ValueError):
+        Server(budget_bytes=10 ** 6, chunk_steps=3, backend=FakeBackend())
