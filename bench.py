@@ -173,6 +173,76 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """Serving form: cavity solves with K log-uniform in [2e3, 2e5], N uniform in 3..6, steps
+    uniform in [100, 2000], FP32 (seed 5). Capacity = requests / makespan of the plain FIFO loop
+    with everything queued at t = 0; then Poisson arrivals at 0.5, 1 and 2 times that rate,
+    served with continuous admission (8 slots, 64 GiB budget) and with the FIFO loop."""
+    import math
+
+    import numpy as np
+
+    import dginputs
+    from paper_0901_1024_amd.serve import Request, Server, summary
+
+    g = np.random.Generator(np.random.PCG64(dginputs.SEED_ARRIVALS))
+    specs = []
+    for i in range(args.serve_requests):
+        kt = math.exp(g.uniform(math.log(2e3), math.log(2e5)))
+        nx = max(1, int(math.floor((kt / 6.0) ** (1.0 / 3.0))))
+        nz = max(1, int(round(kt / (6.0 * nx * nx))))
+        specs.append((nx, nz, int(g.integers(3, 7)), int(g.integers(100, 2001))))
+    gaps = g.exponential(1.0, size=len(specs))
+
+    def cavity(x):
+        return dginputs.cavity_tm110(x[0], x[1], x[2], 0.0)
+
+    meshes = [dginputs.kuhn_cube(0, jitter=0.15, permute=True, seed_jitter=300 + i, seed_perm=400 + i,
+                                 nx=nx, ny=nx, nz=nz) for i, (nx, nz, _, _) in enumerate(specs)]
+
+    def requests(rate):
+        t = 0.0
+        out = []
+        for i, ((nx, nz, N, steps), (v, e)) in enumerate(zip(specs, meshes)):
+            out.append(Request(rid=i, arrival=t, vxyz=v, etov=e, order=N, steps=steps, init=cavity))
+            if rate:
+                t += gaps[i] / rate
+        return out
+
+    budget = 64 * 2 ** 30
+    fifo = lambda: Server(budget, slots=1, chunk_steps=args.serve_chunk)
+    served = lambda: Server(budget, slots=args.serve_slots, chunk_steps=args.serve_chunk)
+    base = summary(fifo().run(requests(0.0)))
+    cap = base["solves_per_s"]
+    print(f"capacity (FIFO, all queued): {cap:.3f} solves/s", file=sys.stderr, flush=True)
+    sweep = []
+    for mult in (0.5, 1.0, 2.0):
+        rate = mult * cap
+        a = summary(served().run(requests(rate)))
+        b = summary(fifo().run(requests(rate)))
+        print(f"rate {mult}x: served {a['solves_per_s']:.3f}/s p50 {a['p50_latency_s']:.3f} p99 "
+              f"{a['p99_latency_s']:.3f} | fifo {b['solves_per_s']:.3f}/s p50 {b['p50_latency_s']:.3f} "
+              f"p99 {b['p99_latency_s']:.3f}", file=sys.stderr, flush=True)
+        sweep.append({"rate_x_capacity": mult, "arrival_rate": rate, "served": a, "fifo": b})
+    top = sweep[-1]
+    Ks = [6 * nx * nx * nz for nx, nz, _, _ in specs]
+    out = {
+        "metric": "solves/s + p50/p99 latency, continuous admission vs plain FIFO loop",
+        "value": round(top["served"]["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(specs)} cavity solves, K log-uniform in [2e3, 2e5] (total {sum(Ks)}), "
+                               "N uniform in 3..6, steps uniform in [100, 2000], FP32, Poisson arrivals (seed 5)",
+                   "slots": args.serve_slots, "chunk_steps": args.serve_chunk, "budget_bytes": budget},
+        "capacity_fifo_solves_per_s": cap,
+        "at_2x_rate": {"served_p50_s": top["served"]["p50_latency_s"], "served_p99_s": top["served"]["p99_latency_s"],
+                       "fifo_solves_per_s": top["fifo"]["solves_per_s"], "fifo_p50_s": top["fifo"]["p50_latency_s"],
+                       "fifo_p99_s": top["fifo"]["p99_latency_s"]},
+        "sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +256,11 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="batched form: 64 meshes of mixed size and order, batched vs plain loop")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving form: Poisson arrivals of cavity solves, continuous admission vs FIFO")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-chunk", type=int, default=64)
     ap.add_argument("--material", action="store_true",
                     help="heterogeneous medium (eps, mu log-uniform in [1, 4]) with absorbing z = 1 faces")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -202,6 +277,9 @@ def main():
 
     if args.batch:
         run_batch(args)
+        return
+    if args.serve:
+        run_serve(args)
         return
     if args.copy_calibration:
         n = 256 * 1024 * 1024 // 4
