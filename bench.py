@@ -243,6 +243,71 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_precision_sweep(args):
+    """Precision form: the (1,1,0) cavity mode on jittered cubes, run to t = T in FP64 and FP32
+    with the same step; per-field relative L2 difference FP32 vs FP64, energy drift
+    E32(t)/E64(t) - 1, and the error of both against the exact mode."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import dginputs
+    import paper_0901_1024_amd as P
+    from oracle import maxwell as W
+    from oracle import mesh as Mm
+    from oracle import refelem as R
+
+    results = []
+    for N, n in ((5, args.sweep_n5), (7, args.sweep_n7)):
+        v, e = dginputs.kuhn_cube(n, jitter=0.15, permute=True)
+        m = Mm.Mesh(v, e, R.ref_element(N), compute_maps=False)
+        u0 = dginputs.cavity_tm110(*m.x, 0.0)
+        exact = dginputs.cavity_tm110(*m.x, args.sweep_t)
+        row = {"order": N, "K": int(m.K), "t": args.sweep_t}
+        fields = {}
+        for prec in ("f64", "f32"):
+            s = P.Solver(v, e, N, prec)
+            s.set_fields(u0.astype(s.dtype))
+            dt0 = s.stable_dt(0.5)
+            nsteps = int(math.ceil(args.sweep_t / dt0))
+            dt = args.sweep_t / nsteps
+            e0 = s.energy()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done = 0
+            while done < nsteps:
+                k = min(500, nsteps - done)
+                s.solve(dt, k)
+                torch.cuda.synchronize()
+                done += k
+                print(f"  N={N} {prec}: {done}/{nsteps} steps", file=sys.stderr, flush=True)
+            sec = time.perf_counter() - t0
+            u = s.get_fields().astype(np.float64)
+            fields[prec] = u
+            err, nrm = W.l2_error(m, u, exact)
+            flops = 5 * nsteps * m.K * flops_per_elem_stage(N)
+            row[prec] = {"steps": nsteps, "dt": dt, "seconds": round(sec, 3),
+                         "gflops": round(flops / sec / 1e9, 1), "energy_0": e0, "energy_T": s.energy(),
+                         "rel_error_vs_exact": err / nrm}
+            s.free()
+        d = fields["f32"] - fields["f64"]
+        ref = np.linalg.norm(fields["f64"])
+        row["f32_vs_f64_rel_per_field"] = [float(np.linalg.norm(d[f]) / ref) for f in range(6)]
+        row["f32_vs_f64_rel"] = float(np.linalg.norm(d) / ref)
+        row["energy_drift_f32_over_f64"] = row["f32"]["energy_T"] / row["f64"]["energy_T"] - 1.0
+        results.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    out = {"metric": "precision sweep: FP32 vs FP64 error, energy drift, error vs exact mode",
+           "value": results[0]["f32_vs_f64_rel"], "unit": "relative L2", "n_gpus": 1,
+           "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": f"(1,1,0) cavity mode to t={args.sweep_t}, jittered permuted cubes, "
+                                  f"N=5 on 6*{args.sweep_n5}^3 and N=7 on 6*{args.sweep_n7}^3 tets, "
+                                  "FP64 and FP32, same step (CFL 0.5)"},
+           "results": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +321,11 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="batched form: 64 meshes of mixed size and order, batched vs plain loop")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="precision form: cavity mode in FP64 and FP32 at N = 5 and 7")
+    ap.add_argument("--sweep-t", type=float, default=1.0)
+    ap.add_argument("--sweep-n5", type=int, default=32)
+    ap.add_argument("--sweep-n7", type=int, default=16)
     ap.add_argument("--serve", action="store_true",
                     help="serving form: Poisson arrivals of cavity solves, continuous admission vs FIFO")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -280,6 +350,9 @@ def main():
         return
     if args.serve:
         run_serve(args)
+        return
+    if args.precision_sweep:
+        run_precision_sweep(args)
         return
     if args.copy_calibration:
         n = 256 * 1024 * 1024 // 4

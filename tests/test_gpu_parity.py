@@ -108,6 +108,28 @@ def test_fp32_full_size_n4_sampled():
     assert s.energy() <= e0 * (1 + 1e-6)
 
 
+def test_fp32_full_size_n5_sampled():
+    """6 * 32^3 = 196,608 jittered, permuted tets, N = 5, FP32 (the 8-element MFMA kernel at the
+    size of the precision sweep); sampled right-hand side and one RK step against the oracle."""
+    say("case: N=5 K=196608 f32 full size, sampled")
+    v, e, m, u0 = problem(5, 32, jitter=0.15, permute=True, compute_maps=False)
+    s = P.Solver(v, e, 5, "f32", reorder=1)
+    u32 = rounded(u0, "f32")
+    g = np.random.default_rng(12)
+    sample = np.unique(np.concatenate([g.choice(m.K, 800, replace=False), [0, m.K - 1]]))
+    r = gpu_rhs(s, u32)
+    err = rel_l2(r[:, sample], W.rhs_at(m, u32, sample))
+    say("  sampled rhs rel", err)
+    assert err <= TOL["f32"]
+    dt = W.stable_dt(m)
+    s.set_fields(u32)
+    s.rk_step(dt)
+    step_sample = sample[:12]
+    err1 = rel_l2(s.get_fields()[:, step_sample], W.lsrk4_step_at(m, u32, dt, step_sample))
+    say("  sampled 1-step rel", err1)
+    assert err1 <= TOL["f32"]
+
+
 def test_reorder_and_repeat_are_bitwise_identical():
     v, e, m, u0 = problem(4, 3, jitter=0.15, permute=True)
     a = P.Solver(v, e, 4, "f64", reorder=1)
