@@ -1254,19 +1254,6 @@ void opfrag_source(int N, int w, int* n, int* blk, int* col) {
   *n = *blk = *col = -1;
 }
 
-int tile_elems(int N) {
-  switch (N) {
-    case 1: return Dims<1>::E;
-    case 2: return Dims<2>::E;
-    case 3: return Dims<3>::E;
-    case 4: return Dims<4>::E;
-    case 5: return Dims<5>::E;
-    case 6: return Dims<6>::E;
-    case 7: return Dims<7>::E;
-  }
-  return 0;
-}
-
 hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
                         hipStream_t s) {
   if (!f64 && ops.opfrag) {

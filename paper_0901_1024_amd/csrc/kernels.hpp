@@ -42,9 +42,6 @@ struct StageArgs {
   double a, b, dt;   // stage coefficients (stage mode only)
 };
 
-// Elements per workgroup tile of the stage kernel for order N.
-int tile_elems(int N);
-
 // One RHS evaluation (stage == false) or one fused LSRK4 stage (stage == true).
 hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
                         hipStream_t s);

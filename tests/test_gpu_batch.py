@@ -84,3 +84,23 @@ def test_batch_matches_the_oracle():
         for _ in range(2):
             uo, res = W.lsrk4_step(m, uo, dts[i], res)
         assert rel_l2(got[:, b.mesh_slice(i)], uo) <= TOL["f64"]
+
+
+def test_batch_time_step_errors():
+    import ctypes
+    meshes = batch_meshes("f32")[:2]
+    b = P.BatchSolver(meshes, 3, "f32")
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        b.set_dts(np.array([1e-3, -1.0]))
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        b.set_dts(np.array([1e-3, np.nan]))
+    with pytest.raises(P.DGError, match="DG_E_ARG"):
+        b.set_dts(np.array([1e-3]))
+    s = P.Solver(meshes[0]["vxyz"], meshes[0]["etov"], 3, "f32")
+    d = np.array([1e-3])
+    rc = P.lib().dg_set_batch_dt(s._h, d.ctypes.data_as(ctypes.c_void_p), None)
+    assert rc == P.DG_E_ARG          # not a batch handle
+    c = ctypes.c_int32()
+    first = np.zeros(2, dtype=np.int32)
+    assert P.lib().dg_batch_info(s._h, ctypes.byref(c), first.ctypes.data_as(ctypes.c_void_p)) == 0
+    assert c.value == 1 and list(first) == [0, s.K]
