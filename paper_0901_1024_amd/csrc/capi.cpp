@@ -33,7 +33,8 @@ constexpr double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 /
                             2277821191437.0 / 14882151754819.0};
 
 struct Layout {
-  size_t state = 0;  // bytes of one [K][6][Np] array
+  size_t state = 0;   // bytes of one canonical [6][K][Np] array
+  size_t istate = 0;  // bytes of one internal [K][6][S] array (S = dgk::row_stride)
   size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
       off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, off_geo_dt, off_mat_dt, total;
   size_t opcat_bytes = 0, mat_bytes = 0, geo_dt_bytes = 0, mat_dt_bytes = 0;
@@ -55,10 +56,11 @@ Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool
     return at;
   };
   L.state = size_t(K) * 6 * Np * ts;
-  L.off_u0 = take(L.state);
-  L.off_u1 = take(L.state);
-  L.off_res = take(L.state);
-  L.off_tmp = take(L.state);
+  L.istate = size_t(K) * 6 * dgk::row_stride(N, ts == 8) * ts;
+  L.off_u0 = take(L.istate);
+  L.off_u1 = take(L.istate);
+  L.off_res = take(L.istate);
+  L.off_tmp = take(L.istate);   // an internal array, or a canonical one (state <= istate)
   L.off_geo = take(size_t(K) * dgh::kGeoStride * ts);
   L.off_fcode = take(size_t(K) * 4 * sizeof(int32_t));
   L.off_ops = take((size_t(4) * Np * Np + size_t(Np) * 4 * Nfp) * ts);
@@ -101,7 +103,7 @@ struct dg_handle {
   bool batch = false;
   std::vector<int32_t> mesh_first, mesh_of;
   std::vector<double> geo_int;
-  int N = 0, Np = 0, Nfp = 0, K = 0, prec = 0, device = -1;
+  int N = 0, Np = 0, S = 0, Nfp = 0, K = 0, prec = 0, device = -1;
   size_t ts = 8;
   Layout lay;
   char* ws = nullptr;
@@ -216,9 +218,9 @@ int upload(dg_handle* h, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_nbr), nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_elem_of), M.elem_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_pos_of), M.pos_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(h->u(0), 0, h->lay.state, s));
-  HIP_TRY(hipMemsetAsync(h->u(1), 0, h->lay.state, s));
-  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.state, s));
+  HIP_TRY(hipMemsetAsync(h->u(0), 0, h->lay.istate, s));
+  HIP_TRY(hipMemsetAsync(h->u(1), 0, h->lay.istate, s));
+  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.istate, s));
   HIP_TRY(hipStreamSynchronize(s));  // host staging buffers die at return
   return DG_OK;
 }
@@ -393,6 +395,7 @@ int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32
   h->K = mesh->K;
   h->prec = opts->precision;
   h->ts = h->f64() ? 8 : 4;
+  h->S = dgk::row_stride(h->N, h->f64());
   h->device = opts->device;
   h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty(), h->batch);
   if (h->device >= 0) {
@@ -494,8 +497,8 @@ int dg_set_fields(dg_handle* h, const void* u, int on_device, void* stream) {
     src = h->at(h->lay.off_tmp);
   }
   HIP_TRY(dgk::launch_to_internal(h->f64(), src, h->u(h->cur),
-                                  static_cast<const int32_t*>(h->at(h->lay.off_elem_of)), h->K, h->Np, s));
-  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.state, s));
+                                  static_cast<const int32_t*>(h->at(h->lay.off_elem_of)), h->K, h->Np, h->S, s));
+  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.istate, s));
   if (!on_device) HIP_TRY(hipStreamSynchronize(s));
   return DG_OK;
 }
@@ -509,7 +512,7 @@ int dg_get_fields(const dg_handle* h, void* u, int on_device, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* dst = on_device ? u : h->at(h->lay.off_tmp);
   HIP_TRY(dgk::launch_to_canonical(h->f64(), h->u(h->cur), dst,
-                                   static_cast<const int32_t*>(h->at(h->lay.off_pos_of)), h->K, h->Np, s));
+                                   static_cast<const int32_t*>(h->at(h->lay.off_pos_of)), h->K, h->Np, h->S, s));
   if (!on_device) {
     HIP_TRY(hipMemcpyAsync(u, dst, h->lay.state, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -527,11 +530,11 @@ int dg_rhs(dg_handle* h, const void* u_dev, void* rhs_dev, void* stream) {
   void* in = h->u(1 - h->cur);  // the spare state buffer is free between steps
   void* out = h->at(h->lay.off_tmp);
   HIP_TRY(dgk::launch_to_internal(h->f64(), u_dev, in, static_cast<const int32_t*>(h->at(h->lay.off_elem_of)),
-                                  h->K, h->Np, s));
+                                  h->K, h->Np, h->S, s));
   rc = stage_launch(h, false, in, out, 0, 0, 0, s);
   if (rc) return rc;
   HIP_TRY(dgk::launch_to_canonical(h->f64(), out, rhs_dev, static_cast<const int32_t*>(h->at(h->lay.off_pos_of)),
-                                   h->K, h->Np, s));
+                                   h->K, h->Np, h->S, s));
   return DG_OK;
 }
 

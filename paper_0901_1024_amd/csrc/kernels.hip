@@ -31,6 +31,13 @@ struct Dims {
   static constexpr int E = (kThreads / Np) > 0 ? (kThreads / Np) : 1;
 };
 
+// Words per (element, field) row of the internal field arrays [K][6][S]: Np, padded to a
+// multiple of 4 (pad words zero) for the orders that the FP32 contraction kernels serve, so
+// that their tiles move in aligned 16-byte chunks.
+constexpr bool contraction_order(int N) { return N >= 3 && N <= 6; }
+template <typename T, int N>
+constexpr int kRowStride = (sizeof(T) == 4 && contraction_order(N)) ? (Dims<N>::Np + 3) / 4 * 4 : Dims<N>::Np;
+
 // Workgroups are dispatched round-robin over the XCDs; give every XCD a contiguous range of
 // tiles so that neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
@@ -183,9 +190,10 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
 // its 16 blocks are read as (k-group g, row quad) pairs, so lane (row, g) supplies the value
 // it already holds for the 16x16x4 step, the tail operator supplies column c of k-group g,
 // and a sum over the four k-groups (cross-lane) finishes the tail. The volume part of the
-// operand is formed on the fly from a padded copy of the field tile in LDS; the face part
-// (Fscale/2 * flux) is materialised in LDS. Every operand and operator read is a 16-byte LDS
-// read that feeds four k-steps, so the contraction issues few LDS instructions and waits.
+// operand is formed on the fly from the field tile in LDS, whose rows are padded to a
+// multiple of 4 nodes; the face part (Fscale/2 * flux) is materialised in LDS. Every operand
+// and operator read is a 16-byte LDS read that feeds four k-steps, so the contraction issues
+// few LDS instructions and waits.
 //
 // k-steps of the 16x16x4 contraction (lane group g = lane / 16 holds k-index g of each step):
 //   volume quads  (jb, mu), jb < NPP / 16:  4 steps, group g at column 16 jb + 4 g + s of D_mu;
@@ -198,11 +206,13 @@ struct MDims {
   static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, Nf4 = Dims<N>::Nf4;
   static constexpr int E = 16;                       // elements per tile
   static constexpr int ROWS = 6 * E;                 // (field, element) rows, field-major
-  static constexpr int TW = E * 6 * Np;              // words in a tile of fields
-  static constexpr int TW4 = TW / 4;                 // float4 chunks in a tile
-  static constexpr int CPT = (TW4 + kThreads - 1) / kThreads;   // float4 chunks per thread
   static constexpr int NPP = (Np + 3) / 4 * 4;       // volume block per direction, padded
-  static constexpr int ES = 6 * NPP + 4;             // element stride of the padded copy (= 4 mod 8)
+  static constexpr int ES = 6 * NPP + 4;             // element stride of the padded tile (= 4 mod 8)
+  static constexpr int PC = NPP / 4;                 // 16-byte chunks per padded row
+  static constexpr int LAST = Np - 4 * (PC - 1);     // field words in the last chunk of a row
+  static constexpr int TC = 6 * E * PC;              // chunks per tile
+  static constexpr int CPC = (TC + kThreads - 1) / kThreads;   // chunks per thread
+  static_assert(ES % 4 == 0, "element rows of the padded tile are 16-byte aligned");
   static constexpr int NF = (Nf4 + 15) / 16 * 16;    // face block, padded
   static constexpr int RSL = NF + 4;                 // flux row stride (= 4 mod 8)
   static constexpr int KV = 3 * NPP;                 // volume part of the contraction
@@ -224,15 +234,14 @@ struct MDims {
   static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
   static_assert(NT == 1 || NT == 2 || NT == 4, "a wave's tiles must share one column tile");
   static_assert(TAIL <= 4, "the tail is one 4-column block");
-  static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
-  // after the contraction the flux rows are free for the rhs staging [e][f][n]
-  static_assert(TW <= ROWS * RSL, "staging must fit in the flux rows");
+  // after the contraction the flux rows are free for the rhs staging (laid out like up_s)
+  static_assert(E * ES <= ROWS * RSL, "staging must fit in the flux rows");
 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // MAT: heterogeneous medium. 1/eps and 1/mu of the tile's elements ride in the unused last
-// words of each element row of the padded copy (up_s) and scale the operand coefficients;
+// words of each element row of the padded tile (up_s) and scale the operand coefficients;
 // the face weights (material record) are read with the neighbour traces.
 template <int N, bool STAGE, bool MAT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void mfma_stage_kernel(
@@ -243,25 +252,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   using D = MDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
                 NF = D::NF, KV = D::KV, KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT,
-                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, FIT = D::FIT, TW = D::TW,
-                TW4 = D::TW4, CPT = D::CPT, VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF,
+                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, FIT = D::FIT,
+                PC = D::PC, LAST = D::LAST, TC = D::TC, CPC = D::CPC, VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF,
                 NQ = D::NQ;
   constexpr int G = dgh::kGeoStride;
   constexpr int GW = E * G;                                   // words of geometry per tile
   constexpr int GPT = (GW + kThreads - 1) / kThreads;
-  __shared__ __align__(16) float us[TW];              // field tile [e][f][n]
-  __shared__ __align__(16) float up_s[E * ES];        // padded copy [e][f][NPP], zero pad columns
+  // field tile [e][f][NPP]: rows padded to NPP words (pad columns zero), element stride ES
+  __shared__ __align__(16) float up_s[E * ES];
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // Fscale/2 * flux [f E + e][fj]; later staging
   __shared__ __align__(16) float bfs[NT * KS * 64];   // operator fragments
   __shared__ __align__(16) float tops[TAIL > 0 ? KS * 16 : 4];  // tail operator fragments
   __shared__ float gt[GW];                            // geometric records of the tile
-  __shared__ int32_t fc[E * 4];                       // face records of the tile
+  __shared__ int32_t fcb[2][E * 4];                   // face records: this tile, the next
   __shared__ uint8_t nbr_s[96 * NFP];                 // neighbour node table
   __shared__ uint8_t fm_s[4 * NFP];                   // face node lists
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
   const int g4 = lane >> 4, li = lane & 15;
+  // The field arrays hold rows of NPP words (pad words zero), [K][6][NPP]: word q of a tile
+  // sits at slot(q) of up_s, whose element rows are ES apart. Chunk c (16 bytes) of a tile is
+  // aligned both in the arrays (words 4c ..) and in up_s (slot(4c) ..).
+  auto slot = [](int q) __attribute__((always_inline)) {
+    const int e = q / (6 * NPP);
+    return e * ES + (q - e * 6 * NPP);
+  };
+  // zero the pad words of the last chunk of a row (they carry no node)
+  auto pad_zero = [](int c, floatx4 v) __attribute__((always_inline)) {
+    if (LAST < 4 && c % PC == PC - 1) {
+      if (LAST <= 3) v.w = 0.f;
+      if (LAST <= 2) v.z = 0.f;
+      if (LAST <= 1) v.y = 0.f;
+    }
+    return v;
+  };
 
   // Persistent schedule: workgroups are dispatched round-robin over the XCDs; XCD x owns the
   // contiguous tile range [x TX, (x+1) TX) and its workgroups sweep it together, so at any time
@@ -280,106 +305,109 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
   if (TAIL > 0)
     for (int q = tid; q < KS * 16; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
+  // the pad columns of up_s are never written again
+  for (int q = tid; q < E * ES; q += kThreads) up_s[q] = 0.f;
+  __syncthreads();
 
-  // prefetch registers: fields, geometry and face records of the next tile
-  floatx4 pu[CPT];
+  // Prefetch registers: fields and geometry of the next tile, the neighbour traces of its
+  // face nodes, and the face records of the tile after it. Every thread loads every slot
+  // (indices clamped): exec-masked loads make the compiler wait for all outstanding loads
+  // before reusing their registers. In the material variant the face-node slot of this
+  // thread is made opaque so that its index arithmetic is not hoisted out of the tile loop.
+  int tq = tid;
+  if (MAT) asm volatile("" : "+v"(tq));
+  floatx4 pu[CPC];
   float pg[GPT];
+  float nup[FIT][6];   // exterior traces u+ of the face nodes tq + r kThreads (all six fields)
   int32_t pf = 0;
   float pm = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
-  // Inlined so that the prefetch arrays stay in registers. Every thread loads every slot
-  // (indices clamped into the tile): exec-masked loads make the compiler wait for all
-  // outstanding loads before reusing their registers.
+  const size_t fc_last = size_t(K) * 4 - 1;
   auto prefetch = [&](int t) __attribute__((always_inline)) {
     if (t * E + E <= K) {   // full tiles only; a ragged tile is read directly
-      const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NP);
+      const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NPP);
 #pragma unroll
-      for (int r = 0; r < CPT; ++r) pu[r] = s4[min(tid + r * kThreads, TW4 - 1)];
+      for (int j = 0; j < CPC; ++j) pu[j] = s4[min(tid + j * kThreads, TC - 1)];
 #pragma unroll
       for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * kThreads, GW - 1)];
-      pf = fcode[size_t(t) * E * 4 + min(tid, E * 4 - 1)];
       if (MAT) {
         const int q = min(tid, 2 * E - 1);
         pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
       }
     }
+    pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
   };
+  // neighbour traces of tile t from its face records fcv (wall and absorbing faces, and slots
+  // past the tile, read their own element: the values are not used)
+  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+    const int e0 = t * E, nl = min(E, K - e0);
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = min(tq + r * kThreads, nl * NF4 - 1);
+      const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+      const int code = fcv[e * 4 + f];
+      const int ci = code >= 0 ? code : 0;
+      const int nn = nbr_s[((f * 4 + (ci & 3)) * 6 + ((ci >> 2) & 7)) * NFP + j];
+      const float* p = u_in + (code >= 0 ? size_t(ci >> 5) * 6 * NPP + nn : size_t(e0 + e) * 6 * NPP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nup[r][c] = p[c * NPP];
+    }
+  };
+  int par = 0;   // fcb[par]: face records of this tile; fcb[par ^ 1]: of the next one
+  if (tid < E * 4) {
+    fcb[0][tid] = fcode[min(size_t(tile) * E * 4 + tid, fc_last)];
+    fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
+  }
+  __syncthreads();
+  gather(tile, fcb[0]);
   prefetch(tile);
+  pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
 
   for (; tile < tend; tile += nwg) {
     const int base = tile * E;
     const int nel = min(E, K - base);
-    const bool full = nel == E;   // a full tile is 16-byte aligned in every [K][6][Np] array
-    const size_t tb = size_t(base) * 6 * NP;
+    const bool full = nel == E;
+    const size_t tb = size_t(base) * 6 * NPP;
 
-    // ---- tile into LDS (from the prefetch registers when full)
+    // ---- tile into LDS (from the prefetch registers when full), one aligned 16-byte write
+    // per chunk. The chunk index is made opaque per tile so that its slot arithmetic is
+    // recomputed rather than kept live.
+    int tz = tid;
+    asm volatile("" : "+v"(tz));
     if (full) {
 #pragma unroll
-      for (int r = 0; r < CPT; ++r) {
-        const int q = tid + r * kThreads;
-        if (q < TW4) reinterpret_cast<floatx4*>(us)[q] = pu[r];
+      for (int j = 0; j < CPC; ++j) {
+        const int c = tz + j * kThreads;
+        if (c < TC) *reinterpret_cast<floatx4*>(up_s + slot(4 * c)) = pu[j];
       }
 #pragma unroll
       for (int r = 0; r < GPT; ++r) {
         const int q = tid + r * kThreads;
         if (q < GW) gt[q] = pg[r];
       }
-      if (tid < E * 4) fc[tid] = pf;
       if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
     } else {
-      for (int q = tid; q < nel * 6 * NP; q += kThreads) us[q] = u_in[tb + q];
+      for (int q = tid; q < nel * 6 * NPP; q += kThreads) up_s[slot(q)] = u_in[tb + q];
       if (MAT)
         for (int q = tid; q < 2 * nel; q += kThreads)
           up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
       for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
-      for (int q = tid; q < nel * 4; q += kThreads) fc[q] = fcode[size_t(base) * 4 + q];
     }
     __syncthreads();
 
-    floatx4 rs4[CPT];
+    floatx4 rs[CPC];
 
-    // ---- face fluxes: fetch every neighbour trace first, then compute. In the material
-    // variant the face-node slot of this thread is made opaque per tile so that its index
-    // arithmetic is recomputed rather than hoisted out of the tile loop and spilled.
-    int tq = tid;
-    if (MAT) asm volatile("" : "+v"(tq));
+    // ---- face fluxes from the exterior traces gathered during the previous tile
+    const int32_t* fc = fcb[par];
     {
-      float up[FIT][6];
       floatx4 wm[FIT];   // MAT: face weights A B C D
+      if (MAT) {
 #pragma unroll
-      for (int r = 0; r < FIT; ++r) {
-        const int q = tq + r * kThreads;
-        if (q < nel * NF4) {
-          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
-          if (MAT)
-            wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
-                                                      dgh::kMatFace + 4 * f);
-          const int code = fc[e * 4 + f];
-          if (code >= 0) {
-            const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
-            const int nn = nbr_s[((f * 4 + f2) * 6 + o) * NFP + j];
-            const int le = nb - base;
-            if (le >= 0 && le < nel) {
-              const float* p = us + le * 6 * NP + nn;
-#pragma unroll
-              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
-            } else {
-              const float* p = u_in + size_t(nb) * 6 * NP + nn;
-#pragma unroll
-              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
-            }
-          }
+        for (int r = 0; r < FIT; ++r) {
+          const int q = min(tq + r * kThreads, nel * NF4 - 1);
+          const int e = q / NF4, f = (q - e * NF4) / NFP;
+          wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
+                                                    dgh::kMatFace + 4 * f);
         }
-      }
-      // padded copy of the tile for the contraction: rows of NPP, columns >= Np zero
-      for (int q = tid; q < nel * 6 * (NPP / 4); q += kThreads) {
-        const int row = q / (NPP / 4), j4 = 4 * (q - row * (NPP / 4));   // row = 6 e + f
-        const float* src = us + row * NP + j4;
-        floatx4 v;
-        v.x = src[0];
-        v.y = j4 + 1 < NP ? src[1] : 0.f;
-        v.z = j4 + 2 < NP ? src[2] : 0.f;
-        v.w = j4 + 3 < NP ? src[3] : 0.f;
-        *reinterpret_cast<floatx4*>(up_s + (row / 6) * ES + (row % 6) * NPP + j4) = v;
       }
       // face columns NF4 .. NF-1 of every row are padding: keep them zero
       for (int q = tid; q < D::ROWS * (NF - NF4); q += kThreads) {
@@ -393,8 +421,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
           const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
           const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
-          const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
-          const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
+          const float* um = up_s + e * ES + fm_s[f * NFP + j];
+          const float Ex = um[0], Ey = um[NPP], Ez = um[2 * NPP], Hx = um[3 * NPP], Hy = um[4 * NPP], Hz = um[5 * NPP];
           float dEx, dEy, dEz, dHx, dHy, dHz;
           const int code = fc[e * 4 + f];
           if (code == dgh::kFacePec) {   // perfectly conducting wall: E+ = -E-, H+ = H-
@@ -404,8 +432,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             dEx = -Ex, dEy = -Ey, dEz = -Ez;
             dHx = -Hx, dHy = -Hy, dHz = -Hz;
           } else {
-            dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
-            dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
+            dEx = nup[r][0] - Ex, dEy = nup[r][1] - Ey, dEz = nup[r][2] - Ez;
+            dHx = nup[r][3] - Hx, dHy = nup[r][4] - Hy, dHz = nup[r][5] - Hz;
           }
           const float ndE = nx * dEx + ny * dEy + nz * dEz;
           const float ndH = nx * dHx + ny * dHy + nz * dHz;
@@ -432,10 +460,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     __syncthreads();
     if (STAGE && full) {
 #pragma unroll
-      for (int r = 0; r < CPT; ++r)   // clamped like the prefetch
-        rs4[r] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + r * kThreads, TW4 - 1)];
+      for (int j = 0; j < CPC; ++j)   // clamped like the prefetch
+        rs[j] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + j * kThreads, TC - 1)];
     }
-    if (tile + nwg < tend) prefetch(tile + nwg);
+    if (tile + nwg < tend) {
+      gather(tile + nwg, fcb[par ^ 1]);
+      prefetch(tile + nwg);
+    }
 
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
     // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
@@ -575,11 +606,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       if (tt < TILES) {
         const int f = tt / NT;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) stage[((4 * g4 + i) * 6 + f) * NP + 16 * nt + li] = acc[t][i];
+        for (int i = 0; i < 4; ++i) stage[(4 * g4 + i) * ES + f * NPP + 16 * nt + li] = acc[t][i];
         if (TAIL > 0 && nt == 0 && g4 == 0 && (li & 3) < TAIL) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            stage[((4 * (li >> 2) + i) * 6 + f) * NP + 16 * NT + (li & 3)] = tacc[t][i];
+            stage[(4 * (li >> 2) + i) * ES + f * NPP + 16 * NT + (li & 3)] = tacc[t][i];
         }
       }
     }
@@ -587,40 +618,43 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     // ---- update and write out, coalesced
     if (full) {
-      floatx4* o4 = reinterpret_cast<floatx4*>(out + tb);
-      floatx4* r4 = reinterpret_cast<floatx4*>(res + tb);
+      int tw = tid;   // opaque, like tz
+      asm volatile("" : "+v"(tw));
 #pragma unroll
-      for (int r = 0; r < CPT; ++r) {
-        const int q = tid + r * kThreads;
-        if (q < TW4) {
-          const floatx4 h = reinterpret_cast<const floatx4*>(stage)[q];
+      for (int j = 0; j < CPC; ++j) {
+        const int c = tw + j * kThreads;
+        if (c < TC) {
+          const int o = slot(4 * c);
+          const floatx4 h = *reinterpret_cast<const floatx4*>(stage + o);
           if (STAGE) {
-            const floatx4 u = reinterpret_cast<const floatx4*>(us)[q];
-            floatx4 rv;
-            rv.x = ca * rs4[r].x + cdt * h.x;
-            rv.y = ca * rs4[r].y + cdt * h.y;
-            rv.z = ca * rs4[r].z + cdt * h.z;
-            rv.w = ca * rs4[r].w + cdt * h.w;
-            r4[q] = rv;
-            o4[q] = floatx4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w};
+            const floatx4 u = *reinterpret_cast<const floatx4*>(up_s + o);
+            const floatx4 rv = pad_zero(c, floatx4{ca * rs[j].x + cdt * h.x, ca * rs[j].y + cdt * h.y,
+                                                   ca * rs[j].z + cdt * h.z, ca * rs[j].w + cdt * h.w});
+            reinterpret_cast<floatx4*>(res + tb)[c] = rv;
+            reinterpret_cast<floatx4*>(out + tb)[c] =
+                floatx4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w};
           } else {
-            o4[q] = h;
+            reinterpret_cast<floatx4*>(out + tb)[c] = pad_zero(c, h);
           }
         }
       }
     } else {
-      for (int q = tid; q < nel * 6 * NP; q += kThreads) {
-        const float h = stage[q];
+      for (int q = tid; q < nel * 6 * NPP; q += kThreads) {
+        const bool node = q % NPP < NP;   // pad words stay zero
+        const float h = node ? stage[slot(q)] : 0.f;
         if (STAGE) {
-          const float rv = ca * res[tb + q] + cdt * h;
+          const float rv = node ? ca * res[tb + q] + cdt * h : 0.f;
           res[tb + q] = rv;
-          out[tb + q] = us[q] + cb * rv;
+          out[tb + q] = up_s[slot(q)] + cb * rv;
         } else {
           out[tb + q] = h;
         }
       }
     }
-    __syncthreads();   // the next tile overwrites us, gt, fc and gl
+    // face records of the tile after next replace those of this tile
+    if (tile + 2 * nwg < tend && tid < E * 4) fcb[par][tid] = pf;
+    par ^= 1;
+    __syncthreads();   // the next tile overwrites up_s, gt, fcb and gl
   }
 }
 
@@ -1079,20 +1113,20 @@ hipError_t launch_stage_t(bool stage, const OpsView& ops, const StageArgs& a, hi
 
 template <typename T>
 __global__ void to_internal_kernel(const T* __restrict__ canon, T* __restrict__ internal,
-                                   const int32_t* __restrict__ elem_of, int K, int Np) {
-  const int64_t total = int64_t(K) * 6 * Np;
+                                   const int32_t* __restrict__ elem_of, int K, int Np, int S) {
+  const int64_t total = int64_t(K) * 6 * S;
   for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < total;
        q += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = q / (6 * Np);
-    const int rem = int(q - i * 6 * Np);
-    const int c = rem / Np, n = rem - c * Np;
-    internal[q] = canon[(int64_t(c) * K + elem_of[i]) * Np + n];
+    const int64_t i = q / (6 * S);
+    const int rem = int(q - i * 6 * S);
+    const int c = rem / S, n = rem - c * S;
+    internal[q] = n < Np ? canon[(int64_t(c) * K + elem_of[i]) * Np + n] : T(0);
   }
 }
 
 template <typename T>
 __global__ void to_canonical_kernel(const T* __restrict__ internal, T* __restrict__ canon,
-                                    const int32_t* __restrict__ pos_of, int K, int Np) {
+                                    const int32_t* __restrict__ pos_of, int K, int Np, int S) {
   const int64_t total = int64_t(K) * 6 * Np;
   for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < total;
        q += int64_t(gridDim.x) * blockDim.x) {
@@ -1100,7 +1134,7 @@ __global__ void to_canonical_kernel(const T* __restrict__ internal, T* __restric
     const int64_t rem = q - c * K * Np;
     const int64_t k = rem / Np;
     const int n = int(rem - k * Np);
-    canon[q] = internal[(int64_t(pos_of[k]) * 6 + c) * Np + n];
+    canon[q] = internal[(int64_t(pos_of[k]) * 6 + c) * S + n];
   }
 }
 
@@ -1108,21 +1142,21 @@ template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void energy_kernel(const T* __restrict__ u, const T* __restrict__ M,
                                                           const T* __restrict__ geo, const T* __restrict__ mat,
                                                           int K, double* __restrict__ partial) {
-  constexpr int NP = Dims<N>::Np;
+  constexpr int NP = Dims<N>::Np, NS = kRowStride<T, N>;
   __shared__ double red[kThreads];
   double acc = 0.0;
   const int e0 = blockIdx.x * kEnergyBlockElems;
   const int e1 = min(K, e0 + kEnergyBlockElems);
   for (int q = threadIdx.x; q < (e1 - e0) * NP; q += kThreads) {
     const int e = e0 + q / NP, i = q % NP;
-    const T* ue = u + size_t(e) * 6 * NP;
+    const T* ue = u + size_t(e) * 6 * NS;
     double s = 0.0;
     for (int c = 0; c < 6; ++c) {
       double mu = 0.0;
-      for (int j = 0; j < NP; ++j) mu += double(M[i * NP + j]) * double(ue[c * NP + j]);
+      for (int j = 0; j < NP; ++j) mu += double(M[i * NP + j]) * double(ue[c * NS + j]);
       // eps weights the E fields and mu the H fields in a medium
       const double w = mat ? double(mat[size_t(e) * dgh::kMatStride + (c < 3 ? 2 : 3)]) : 1.0;
-      s += w * mu * double(ue[c * NP + i]);
+      s += w * mu * double(ue[c * NS + i]);
     }
     acc += 0.5 * double(geo[size_t(e) * dgh::kGeoStride + dgh::kGeoJ]) * s;
   }
@@ -1145,16 +1179,24 @@ hipError_t launch_energy_t(const void* u, const void* M, const void* geo, const 
   return hipGetLastError();
 }
 
+// The VALU kernel reads rows of Np words; an order whose rows are padded is served by the
+// contraction kernel only.
+template <typename T, int N>
+hipError_t valu_stage(bool stage, const OpsView& o, const StageArgs& a, hipStream_t s) {
+  if constexpr (kRowStride<T, N> == Dims<N>::Np) return launch_stage_t<T, N>(stage, o, a, s);
+  else return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t dispatch_stage(int N, bool stage, const OpsView& o, const StageArgs& a, hipStream_t s) {
   switch (N) {
-    case 1: return launch_stage_t<T, 1>(stage, o, a, s);
-    case 2: return launch_stage_t<T, 2>(stage, o, a, s);
-    case 3: return launch_stage_t<T, 3>(stage, o, a, s);
-    case 4: return launch_stage_t<T, 4>(stage, o, a, s);
-    case 5: return launch_stage_t<T, 5>(stage, o, a, s);
-    case 6: return launch_stage_t<T, 6>(stage, o, a, s);
-    case 7: return launch_stage_t<T, 7>(stage, o, a, s);
+    case 1: return valu_stage<T, 1>(stage, o, a, s);
+    case 2: return valu_stage<T, 2>(stage, o, a, s);
+    case 3: return valu_stage<T, 3>(stage, o, a, s);
+    case 4: return valu_stage<T, 4>(stage, o, a, s);
+    case 5: return valu_stage<T, 5>(stage, o, a, s);
+    case 6: return valu_stage<T, 6>(stage, o, a, s);
+    case 7: return valu_stage<T, 7>(stage, o, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1191,7 +1233,12 @@ int opcat_words(int N) {
   return 0;
 }
 
-bool mfma_order(int N) { return N >= 3 && N <= 6; }
+bool mfma_order(int N) { return contraction_order(N); }
+
+int row_stride(int N, bool f64) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  return (!f64 && contraction_order(N)) ? (Np + 3) / 4 * 4 : Np;
+}
 
 namespace {
 // Decodes a column k of the padded concatenation [D_r | D_s | D_t] (NPP columns each) + LIFT
@@ -1266,26 +1313,26 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
 }
 
 hipError_t launch_to_internal(bool f64, const void* canon, void* internal, const int32_t* elem_of,
-                              int K, int Np, hipStream_t s) {
-  const int g = grid_for(int64_t(K) * 6 * Np);
+                              int K, int Np, int S, hipStream_t s) {
+  const int g = grid_for(int64_t(K) * 6 * S);
   if (f64)
     to_internal_kernel<double><<<g, kThreads, 0, s>>>(static_cast<const double*>(canon),
-                                                      static_cast<double*>(internal), elem_of, K, Np);
+                                                      static_cast<double*>(internal), elem_of, K, Np, S);
   else
     to_internal_kernel<float><<<g, kThreads, 0, s>>>(static_cast<const float*>(canon),
-                                                     static_cast<float*>(internal), elem_of, K, Np);
+                                                     static_cast<float*>(internal), elem_of, K, Np, S);
   return hipGetLastError();
 }
 
 hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, const int32_t* pos_of,
-                               int K, int Np, hipStream_t s) {
+                               int K, int Np, int S, hipStream_t s) {
   const int g = grid_for(int64_t(K) * 6 * Np);
   if (f64)
     to_canonical_kernel<double><<<g, kThreads, 0, s>>>(static_cast<const double*>(internal),
-                                                       static_cast<double*>(canon), pos_of, K, Np);
+                                                       static_cast<double*>(canon), pos_of, K, Np, S);
   else
     to_canonical_kernel<float><<<g, kThreads, 0, s>>>(static_cast<const float*>(internal),
-                                                      static_cast<float*>(canon), pos_of, K, Np);
+                                                      static_cast<float*>(canon), pos_of, K, Np, S);
   return hipGetLastError();
 }
 

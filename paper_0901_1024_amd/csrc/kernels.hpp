@@ -26,13 +26,16 @@ struct OpsView {
 int opcat_words(int N);
 // Whether the FP32 MFMA stage kernel serves order N.
 bool mfma_order(int N);
+// Words per (element, field) row of the internal field arrays, [K][6][S]: Np, rounded up to a
+// multiple of 4 for the FP32 contraction orders (the pad words are kept zero).
+int row_stride(int N, bool f64);
 // Word w of the fragment-ordered operator of order N holds row n of operator block blk
 // (0, 1, 2 = Dr, Ds, Dt; 3 = LIFT) at column col; it is zero when n, col fall outside the
 // operator (n >= Np, col >= Np for a D block, col >= 4 Nfp for LIFT).
 void opfrag_source(int N, int w, int* n, int* blk, int* col);
 
 struct StageArgs {
-  const void* u_in;  // internal layout [K][6][Np]
+  const void* u_in;  // internal layout [K][6][S], S = row_stride(N, f64)
   void* out;         // rhs (RHS mode) or u_out (stage mode), internal layout
   void* res;         // RK residual, internal layout (stage mode only)
   const void* geo;   // [K][26]
@@ -46,12 +49,12 @@ struct StageArgs {
 hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
                         hipStream_t s);
 
-// Canonical [6][K][Np] <-> internal [K][6][Np] (internal position i holds user element
-// elem_of[i]).
+// Canonical [6][K][Np] <-> internal [K][6][S] (internal position i holds user element
+// elem_of[i]; to_internal writes the pad words as zero).
 hipError_t launch_to_internal(bool f64, const void* canon, void* internal, const int32_t* elem_of,
-                              int K, int Np, hipStream_t s);
+                              int K, int Np, int S, hipStream_t s);
 hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, const int32_t* pos_of,
-                               int K, int Np, hipStream_t s);
+                               int K, int Np, int S, hipStream_t s);
 
 // Partial energies: one double per block of `energy_block_elems` elements written to
 // `partial`; the caller sums them.
