@@ -463,10 +463,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int j = 0; j < CPC; ++j)   // clamped like the prefetch
         rs[j] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + j * kThreads, TC - 1)];
     }
-    if (tile + nwg < tend) {
-      gather(tile + nwg, fcb[par ^ 1]);
-      prefetch(tile + nwg);
-    }
+    if (tile + nwg < tend) prefetch(tile + nwg);
 
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
     // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
@@ -594,6 +591,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           tacc[t][i] = v;
         }
     }
+    // exterior traces of the next tile: issued after the contraction so that their scattered
+    // loads do not hold up its first MFMAs; staging and write-out cover their latency
+    if (tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1]);
     __syncthreads();   // flux rows are read: reuse them for the staging
 
     // ---- stage the right-hand side [e][f][n] in LDS. 16x16x4 result: lane (li, g4), register
