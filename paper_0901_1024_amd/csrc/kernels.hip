@@ -693,14 +693,18 @@ struct HDims {
   static constexpr int NQ = QV + QF;
   static constexpr int FIT = (E * Nf4 + THREADS - 1) / THREADS;
   static constexpr int OPC = NT * KS * 64;            // fragment-ordered operator, no tail
+  // exterior traces gathered one tile ahead (registers live across the contraction) where the
+  // register file allows two waves per SIMD; otherwise at the start of the flux phase
+  static constexpr bool AHEAD = N == 5;
   static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
   static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
+  static_assert(NPP == Np, "rows need no padding: 16-byte chunks of a tile map to the LDS rows");
   static_assert(TW <= ROWS * RSL, "staging must fit in the flux rows");
   static_assert(ROWS % 16 == 0, "whole row tiles");
 };
 
 template <int N, bool STAGE, bool MAT>
-__global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
+__global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void hmfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
     const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
@@ -713,17 +717,21 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
   constexpr int G = dgh::kGeoStride;
   constexpr int GW = E * G;
   constexpr int GPT = (GW + NTH - 1) / NTH;
-  __shared__ __align__(16) float us[TW];              // field tile [e][f][n]
-  __shared__ __align__(16) float up_s[E * ES];        // padded copy [e][f][NPP]
+  __shared__ __align__(16) float up_s[E * ES];        // field tile [e][f][n], element stride ES
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // flux rows [f E + e][fj]; later staging
   __shared__ float gt[GW];
-  __shared__ int32_t fc[E * 4];
+  __shared__ int32_t fcb[2][E * 4];                   // face records: this tile, the next
   __shared__ uint8_t nbr_s[96 * NFP];
   __shared__ uint8_t fm_s[4 * NFP];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int nt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's column tile
   const int g4 = lane >> 4, li = lane & 15;
+  // slot in up_s of word q of a tile of the [K][6][Np] field arrays
+  auto slot = [](int q) __attribute__((always_inline)) {
+    const int e = q / (6 * NP);
+    return e * ES + (q - e * 6 * NP);
+  };
 
   const int nwg = gridDim.x / kXcds;
   const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
@@ -746,10 +754,16 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
   for (int q = tid; q < 96 * NFP; q += NTH) nbr_s[q] = uint8_t(nbrnode[q]);
   for (int q = tid; q < 4 * NFP; q += NTH) fm_s[q] = uint8_t(fmask[q]);
 
+  // prefetch registers, as in the kernel above: fields and geometry of the next tile, the
+  // exterior traces of its face nodes, the face records of the tile after it
+  int tq = tid;
+  asm volatile("" : "+v"(tq));
   floatx4 pu[CPT];
   float pg[GPT];
+  float nup[FIT][6];
   int32_t pf = 0;
   float pm = 0.f;
+  const size_t fc_last = size_t(K) * 4 - 1;
   auto prefetch = [&](int t) __attribute__((always_inline)) {
     if (t * E + E <= K) {
       const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NP);
@@ -757,14 +771,36 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
       for (int r = 0; r < CPT; ++r) pu[r] = s4[min(tid + r * NTH, TW4 - 1)];
 #pragma unroll
       for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * NTH, GW - 1)];
-      pf = fcode[size_t(t) * E * 4 + min(tid, E * 4 - 1)];
       if (MAT) {
         const int q = min(tid, 2 * E - 1);
         pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
       }
     }
+    pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
   };
+  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+    const int e0 = t * E, nl = min(E, K - e0);
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = min(tq + r * NTH, nl * NF4 - 1);
+      const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+      const int code = fcv[e * 4 + f];
+      const int ci = code >= 0 ? code : 0;
+      const int nn = nbr_s[((f * 4 + (ci & 3)) * 6 + ((ci >> 2) & 7)) * NFP + j];
+      const float* p = u_in + (code >= 0 ? size_t(ci >> 5) * 6 * NP + nn : size_t(e0 + e) * 6 * NP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nup[r][c] = p[c * NP];
+    }
+  };
+  int par = 0;
+  if (tid < E * 4) {
+    fcb[0][tid] = fcode[min(size_t(tile) * E * 4 + tid, fc_last)];
+    fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
+  }
+  __syncthreads();
+  if (D::AHEAD) gather(tile, fcb[0]);
   prefetch(tile);
+  pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
 
   for (; tile < tend; tile += nwg) {
     const int base = tile * E;
@@ -776,67 +812,38 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int q = tid + r * NTH;
-        if (q < TW4) reinterpret_cast<floatx4*>(us)[q] = pu[r];
+        if (q < TW4) *reinterpret_cast<floatx4*>(up_s + slot(4 * q)) = pu[r];
       }
 #pragma unroll
       for (int r = 0; r < GPT; ++r) {
         const int q = tid + r * NTH;
         if (q < GW) gt[q] = pg[r];
       }
-      if (tid < E * 4) fc[tid] = pf;
       if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
     } else {
-      for (int q = tid; q < nel * 6 * NP; q += NTH) us[q] = u_in[tb + q];
+      for (int q = tid; q < nel * 6 * NP; q += NTH) up_s[slot(q)] = u_in[tb + q];
       if (MAT)
         for (int q = tid; q < 2 * nel; q += NTH)
           up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
       for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
-      for (int q = tid; q < nel * 4; q += NTH) fc[q] = fcode[size_t(base) * 4 + q];
     }
     __syncthreads();
 
     floatx4 rs4[CPT];
 
     // ---- face fluxes (as in the kernel above)
-    int tq = tid;
-    asm volatile("" : "+v"(tq));
+    const int32_t* fc = fcb[par];
+    if (!D::AHEAD) gather(tile, fc);
     {
-      float up[FIT][6];
       floatx4 wm[FIT];
+      if (MAT) {
 #pragma unroll
-      for (int r = 0; r < FIT; ++r) {
-        const int q = tq + r * NTH;
-        if (q < nel * NF4) {
-          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
-          if (MAT)
-            wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
-                                                      dgh::kMatFace + 4 * f);
-          const int code = fc[e * 4 + f];
-          if (code >= 0) {
-            const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
-            const int nn = nbr_s[((f * 4 + f2) * 6 + o) * NFP + j];
-            const int le = nb - base;
-            if (le >= 0 && le < nel) {
-              const float* p = us + le * 6 * NP + nn;
-#pragma unroll
-              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
-            } else {
-              const float* p = u_in + size_t(nb) * 6 * NP + nn;
-#pragma unroll
-              for (int c = 0; c < 6; ++c) up[r][c] = p[c * NP];
-            }
-          }
+        for (int r = 0; r < FIT; ++r) {
+          const int q = min(tq + r * NTH, nel * NF4 - 1);
+          const int e = q / NF4, f = (q - e * NF4) / NFP;
+          wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
+                                                    dgh::kMatFace + 4 * f);
         }
-      }
-      for (int q = tid; q < nel * 6 * (NPP / 4); q += NTH) {
-        const int row = q / (NPP / 4), j4 = 4 * (q - row * (NPP / 4));   // row = 6 e + f
-        const float* src = us + row * NP + j4;
-        floatx4 v;
-        v.x = src[0];
-        v.y = j4 + 1 < NP ? src[1] : 0.f;
-        v.z = j4 + 2 < NP ? src[2] : 0.f;
-        v.w = j4 + 3 < NP ? src[3] : 0.f;
-        *reinterpret_cast<floatx4*>(up_s + (row / 6) * ES + (row % 6) * NPP + j4) = v;
       }
       for (int q = tid; q < D::ROWS * (NF - NF4); q += NTH) {
         const int row = q / (NF - NF4);
@@ -849,7 +856,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
           const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
           const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
           const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
-          const float* um = us + e * 6 * NP + fm_s[f * NFP + j];
+          const float* um = up_s + e * ES + fm_s[f * NFP + j];
           const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
           float dEx, dEy, dEz, dHx, dHy, dHz;
           const int code = fc[e * 4 + f];
@@ -860,8 +867,8 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
             dEx = -Ex, dEy = -Ey, dEz = -Ez;
             dHx = -Hx, dHy = -Hy, dHz = -Hz;
           } else {
-            dEx = up[r][0] - Ex, dEy = up[r][1] - Ey, dEz = up[r][2] - Ez;
-            dHx = up[r][3] - Hx, dHy = up[r][4] - Hy, dHz = up[r][5] - Hz;
+            dEx = nup[r][0] - Ex, dEy = nup[r][1] - Ey, dEz = nup[r][2] - Ez;
+            dHx = nup[r][3] - Hx, dHy = nup[r][4] - Hy, dHz = nup[r][5] - Hz;
           }
           const float ndE = nx * dEx + ny * dEy + nz * dEz;
           const float ndH = nx * dHx + ny * dHy + nz * dHz;
@@ -979,6 +986,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
         }
       }
     }
+    if (D::AHEAD && tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1]);
     __syncthreads();   // flux rows are read: reuse them for the staging
 
     // ---- stage the right-hand side [e][f][n]: lane (li, g4), register i = row 16 t + 4 g4 + i,
@@ -1007,7 +1015,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
         if (q < TW4) {
           const floatx4 h = reinterpret_cast<const floatx4*>(stage)[q];
           if (STAGE) {
-            const floatx4 u = reinterpret_cast<const floatx4*>(us)[q];
+            const floatx4 u = *reinterpret_cast<const floatx4*>(up_s + slot(4 * q));
             const floatx4 rv = ca * rs4[r] + cdt * h;
             r4[q] = rv;
             o4[q] = u + cb * rv;
@@ -1022,13 +1030,15 @@ __global__ __launch_bounds__(HDims<N>::THREADS) void hmfma_stage_kernel(
         if (STAGE) {
           const float rv = ca * res[tb + q] + cdt * h;
           res[tb + q] = rv;
-          out[tb + q] = us[q] + cb * rv;
+          out[tb + q] = up_s[slot(q)] + cb * rv;
         } else {
           out[tb + q] = h;
         }
       }
     }
-    __syncthreads();
+    if (tile + 2 * nwg < tend && tid < E * 4) fcb[par][tid] = pf;
+    par ^= 1;
+    __syncthreads();   // the next tile overwrites up_s, gt, fcb and gl
   }
 }
 
