@@ -336,12 +336,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
     pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
   };
-  // neighbour traces of tile t from its face records fcv (wall and absorbing faces, and slots
-  // past the tile, read their own element: the values are not used)
-  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+  // neighbour traces of tile t (face-node slots r0 .. r1 - 1 of this thread) from its face
+  // records fcv (wall and absorbing faces, and slots past the tile, read their own element:
+  // the values are not used)
+  auto gather = [&](int t, const int32_t* fcv, int r0, int r1) __attribute__((always_inline)) {
     const int e0 = t * E, nl = min(E, K - e0);
 #pragma unroll
-    for (int r = 0; r < FIT; ++r) {
+    for (int r = r0; r < r1; ++r) {
       const int q = min(tq + r * kThreads, nl * NF4 - 1);
       const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
       const int code = fcv[e * 4 + f];
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
   }
   __syncthreads();
-  gather(tile, fcb[0]);
+  gather(tile, fcb[0], 0, FIT);
   prefetch(tile);
   pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
 
@@ -535,6 +536,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
 #pragma unroll
       for (int fb = 0; fb < QF; ++fb) {
+        // the exterior traces of the next tile are issued in two halves among the last MFMAs
+        // of the contraction, so that the scattered loads overlap matrix work; staging and
+        // write-out then cover their latency
+        if (fb == QF / 2 && tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1], 0, FIT / 2);
         floatx4 xf[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) xf[t] = *reinterpret_cast<const floatx4*>(fl[t] + 16 * fb);
@@ -555,6 +560,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(xs[t], zv[s], tacc[t], 0, 0, 0);
         }
       }
+      if (tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1], FIT / 2, FIT);
 #pragma unroll
       for (int r = 0; r < VR; ++r) {
         float xc1[TPW], xb1[TPW];
@@ -591,9 +597,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           tacc[t][i] = v;
         }
     }
-    // exterior traces of the next tile: issued after the contraction so that their scattered
-    // loads do not hold up its first MFMAs; staging and write-out cover their latency
-    if (tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1]);
     __syncthreads();   // flux rows are read: reuse them for the staging
 
     // ---- stage the right-hand side [e][f][n] in LDS. 16x16x4 result: lane (li, g4), register
