@@ -464,7 +464,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int j = 0; j < CPC; ++j)   // clamped like the prefetch
         rs[j] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + j * kThreads, TC - 1)];
     }
-    if (tile + nwg < tend) prefetch(tile + nwg);
 
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
     // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
@@ -534,6 +533,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           }
         }
       }
+      // the next tile's fields and geometry are requested between the volume and face steps
+      if (tile + nwg < tend) prefetch(tile + nwg);
 #pragma unroll
       for (int fb = 0; fb < QF; ++fb) {
         // the exterior traces of the next tile are issued in two halves among the last MFMAs
