@@ -263,7 +263,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // Fscale/2 * flux [f E + e][fj]; later staging
   __shared__ __align__(16) float bfs[NT * KS * 64];   // operator fragments
   __shared__ __align__(16) float tops[TAIL > 0 ? KS * 16 : 4];  // tail operator fragments
-  __shared__ float gt[GW];                            // geometric records of the tile
+  __shared__ float gt[GW];
+  __shared__ __align__(16) float wmat[MAT ? E * 4 * dgh::kMatFace : 4];   // MAT: face weights [e][f][A B C D]                            // geometric records of the tile
   __shared__ int32_t fcb[2][E * 4];                   // face records: this tile, the next
   __shared__ uint8_t nbr_s[96 * NFP];                 // neighbour node table
   __shared__ uint8_t fm_s[4 * NFP];                   // face node lists
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   float pg[GPT];
   float nup[FIT][6];   // exterior traces u+ of the face nodes tq + r kThreads (all six fields)
   int32_t pf = 0;
-  float pm = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
+  float pm = 0.f, pw = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
   const size_t fc_last = size_t(K) * 4 - 1;
   auto prefetch = [&](int t) __attribute__((always_inline)) {
     if (t * E + E <= K) {   // full tiles only; a ragged tile is read directly
@@ -332,6 +333,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       if (MAT) {
         const int q = min(tid, 2 * E - 1);
         pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
+        const int qw = min(tid, 16 * E - 1);   // word qw % 16 of the face weights of element qw / 16
+        pw = mat[(size_t(t) * E + qw / 16) * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
       }
     }
     pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
@@ -386,11 +389,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (q < GW) gt[q] = pg[r];
       }
       if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * E) wmat[tid] = pw;
     } else {
       for (int q = tid; q < nel * 6 * NPP; q += kThreads) up_s[slot(q)] = u_in[tb + q];
-      if (MAT)
+      if (MAT) {
         for (int q = tid; q < 2 * nel; q += kThreads)
           up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+        for (int q = tid; q < 16 * nel; q += kThreads)
+          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      }
       for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
     }
     __syncthreads();
@@ -406,8 +413,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int r = 0; r < FIT; ++r) {
           const int q = min(tq + r * kThreads, nel * NF4 - 1);
           const int e = q / NF4, f = (q - e * NF4) / NFP;
-          wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
-                                                    dgh::kMatFace + 4 * f);
+          wm[r] = *reinterpret_cast<const floatx4*>(wmat + 16 * e + 4 * f);
         }
       }
       // face columns NF4 .. NF-1 of every row are padding: keep them zero
@@ -724,6 +730,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   __shared__ __align__(16) float up_s[E * ES];        // field tile [e][f][n], element stride ES
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // flux rows [f E + e][fj]; later staging
   __shared__ float gt[GW];
+  __shared__ __align__(16) float wmat[MAT ? E * 4 * dgh::kMatFace : 4];   // MAT: face weights [e][f][A B C D]
   __shared__ int32_t fcb[2][E * 4];                   // face records: this tile, the next
   __shared__ uint8_t nbr_s[96 * NFP];
   __shared__ uint8_t fm_s[4 * NFP];
@@ -766,7 +773,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   float pg[GPT];
   float nup[FIT][6];
   int32_t pf = 0;
-  float pm = 0.f;
+  float pm = 0.f, pw = 0.f;
   const size_t fc_last = size_t(K) * 4 - 1;
   auto prefetch = [&](int t) __attribute__((always_inline)) {
     if (t * E + E <= K) {
@@ -778,6 +785,8 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
       if (MAT) {
         const int q = min(tid, 2 * E - 1);
         pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
+        const int qw = min(tid, 16 * E - 1);   // word qw % 16 of the face weights of element qw / 16
+        pw = mat[(size_t(t) * E + qw / 16) * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
       }
     }
     pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
@@ -824,11 +833,15 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         if (q < GW) gt[q] = pg[r];
       }
       if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * E) wmat[tid] = pw;
     } else {
       for (int q = tid; q < nel * 6 * NP; q += NTH) up_s[slot(q)] = u_in[tb + q];
-      if (MAT)
+      if (MAT) {
         for (int q = tid; q < 2 * nel; q += NTH)
           up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+        for (int q = tid; q < 16 * nel; q += NTH)
+          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      }
       for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
     }
     __syncthreads();
@@ -845,8 +858,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         for (int r = 0; r < FIT; ++r) {
           const int q = min(tq + r * NTH, nel * NF4 - 1);
           const int e = q / NF4, f = (q - e * NF4) / NFP;
-          wm[r] = *reinterpret_cast<const floatx4*>(mat + (size_t(base) + e) * dgh::kMatStride +
-                                                    dgh::kMatFace + 4 * f);
+          wm[r] = *reinterpret_cast<const floatx4*>(wmat + 16 * e + 4 * f);
         }
       }
       for (int q = tid; q < D::ROWS * (NF - NF4); q += NTH) {
