@@ -322,20 +322,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   float nup[FIT][6];   // exterior traces u+ of the face nodes tq + r kThreads (all six fields)
   int32_t pf = 0;
   float pm = 0.f, pw = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
+  // Every prefetch load is issued on every path, its index clamped into its array (a ragged
+  // or missing next tile loads values that are not used): the compiler's wait counts then
+  // hold on every path, so a wait for one load never falls back to waiting for all of them.
   const size_t fc_last = size_t(K) * 4 - 1;
+  const size_t chunk_last = size_t(K) * 6 * NPP / 4 - 1;
+  const floatx4* u4 = reinterpret_cast<const floatx4*>(u_in);
   auto prefetch = [&](int t) __attribute__((always_inline)) {
-    if (t * E + E <= K) {   // full tiles only; a ragged tile is read directly
-      const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NPP);
 #pragma unroll
-      for (int j = 0; j < CPC; ++j) pu[j] = s4[min(tid + j * kThreads, TC - 1)];
+    for (int j = 0; j < CPC; ++j) pu[j] = u4[min(size_t(t) * TC + min(tid + j * kThreads, TC - 1), chunk_last)];
 #pragma unroll
-      for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * kThreads, GW - 1)];
-      if (MAT) {
-        const int q = min(tid, 2 * E - 1);
-        pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
-        const int qw = min(tid, 16 * E - 1);   // word qw % 16 of the face weights of element qw / 16
-        pw = mat[(size_t(t) * E + qw / 16) * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
-      }
+    for (int r = 0; r < GPT; ++r)
+      pg[r] = geo[min(size_t(t) * GW + min(tid + r * kThreads, GW - 1), size_t(K) * G - 1)];
+    if (MAT) {
+      const int q = min(tid, 2 * E - 1);
+      const size_t e = min(size_t(t) * E + q / 2, size_t(K) - 1);
+      pm = mat[e * dgh::kMatStride + (q & 1)];
+      const int qw = min(tid, 16 * E - 1);   // word qw % 16 of the face weights of element qw / 16
+      const size_t ew = min(size_t(t) * E + qw / 16, size_t(K) - 1);
+      pw = mat[ew * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
     }
     pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
   };
@@ -370,6 +375,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int base = tile * E;
     const int nel = min(E, K - base);
     const bool full = nel == E;
+    // the tile whose loads are issued during this one (this tile again when it is the last)
+    const bool more = tile + nwg < tend;
+    const int nxt = more ? tile + nwg : tile;
     const size_t tb = size_t(base) * 6 * NPP;
 
     // ---- tile into LDS (from the prefetch registers when full), one aligned 16-byte write
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int j = 0; j < CPC; ++j) {
         const int c = tz + j * kThreads;
-        if (c < TC) *reinterpret_cast<floatx4*>(up_s + slot(4 * c)) = pu[j];
+        if ((j + 1) * kThreads <= TC || c < TC) *reinterpret_cast<floatx4*>(up_s + slot(4 * c)) = pu[j];
       }
 #pragma unroll
       for (int r = 0; r < GPT; ++r) {
@@ -465,10 +473,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
     }
     __syncthreads();
-    if (STAGE && full) {
+    if (STAGE) {
 #pragma unroll
-      for (int j = 0; j < CPC; ++j)   // clamped like the prefetch
-        rs[j] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + j * kThreads, TC - 1)];
+      for (int j = 0; j < CPC; ++j)   // clamped like the prefetch (a ragged tile reads res directly)
+        rs[j] = reinterpret_cast<const floatx4*>(res)[min(size_t(tile) * TC + min(tid + j * kThreads, TC - 1), chunk_last)];
     }
 
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
@@ -540,13 +548,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         }
       }
       // the next tile's fields and geometry are requested between the volume and face steps
-      if (tile + nwg < tend) prefetch(tile + nwg);
+      prefetch(nxt);
 #pragma unroll
       for (int fb = 0; fb < QF; ++fb) {
         // the exterior traces of the next tile are issued in two halves among the last MFMAs
         // of the contraction, so that the scattered loads overlap matrix work; staging and
         // write-out then cover their latency
-        if (fb == QF / 2 && tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1], 0, FIT / 2);
+        if (fb == QF / 2) gather(nxt, fcb[more ? par ^ 1 : par], 0, FIT / 2);
         floatx4 xf[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) xf[t] = *reinterpret_cast<const floatx4*>(fl[t] + 16 * fb);
@@ -567,7 +575,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(xs[t], zv[s], tacc[t], 0, 0, 0);
         }
       }
-      if (tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1], FIT / 2, FIT);
+      gather(nxt, fcb[more ? par ^ 1 : par], FIT / 2, FIT);
 #pragma unroll
       for (int r = 0; r < VR; ++r) {
         float xc1[TPW], xb1[TPW];
@@ -633,7 +641,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int j = 0; j < CPC; ++j) {
         const int c = tw + j * kThreads;
-        if (c < TC) {
+        if ((j + 1) * kThreads <= TC || c < TC) {
           const int o = slot(4 * c);
           const floatx4 h = *reinterpret_cast<const floatx4*>(stage + o);
           if (STAGE) {
