@@ -181,6 +181,31 @@ def test_degenerate_meshes_single_and_two_tets(N):
         assert rel_l2(gpu_rhs(s, u0), W.rhs(m, u0)) <= TOL["f64"]
 
 
+@pytest.mark.parametrize("N", [3, 4, 5, 6])
+def test_fp32_meshes_smaller_than_a_tile(N):
+    """The FP32 contraction kernels on 1, 2 and 6 elements (one ragged tile, shorter than a
+    tile of the field arrays, so every clamped prefetch index lands inside the arrays): the
+    right-hand side and one RK step against the oracle, in vacuum and in a medium."""
+    one_v = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    two_v = np.vstack([one_v, [[0.9, 0.8, 0.95]]])
+    cube_v, cube_e = dginputs.kuhn_cube(1, jitter=0.1, permute=True)
+    for v, e in ((one_v, np.array([[0, 1, 2, 3]])), (two_v, np.array([[0, 1, 2, 3], [1, 2, 3, 4]])),
+                 (cube_v, cube_e)):
+        m = Mm.Mesh(v, e, R.ref_element(N))
+        u0 = rounded(dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), *m.x), "f32")
+        eps, mu = dginputs.random_materials(e.shape[0])
+        for kw in ({}, dict(eps=eps, mu=mu)):
+            say(f"case: N={N} K={e.shape[0]} f32 {'medium' if kw else 'vacuum'}")
+            s = P.Solver(v, e, N, "f32", **kw)
+            assert rel_l2(gpu_rhs(s, u0), W.rhs(m, u0, **kw)) <= TOL["f32"]
+            dt = W.stable_dt(m) / 4
+            s.set_fields(u0)
+            s.rk_step(dt)
+            uo, _ = W.lsrk4_step(m, u0, dt, **kw)
+            assert rel_l2(s.get_fields(), uo) <= TOL["f32"]
+            s.free()
+
+
 def test_rhs_rejects_bad_buffers():
     import torch
     v, e, m, u0 = problem(2, 1)
