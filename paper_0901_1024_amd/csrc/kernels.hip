@@ -783,19 +783,22 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   int32_t pf = 0;
   float pm = 0.f, pw = 0.f;
   const size_t fc_last = size_t(K) * 4 - 1;
+  // every load issued on every path, indices clamped into the arrays (as in the kernel above)
+  const size_t chunk_last = size_t(K) * 6 * NP / 4 - 1;
+  const floatx4* u4 = reinterpret_cast<const floatx4*>(u_in);
   auto prefetch = [&](int t) __attribute__((always_inline)) {
-    if (t * E + E <= K) {
-      const floatx4* s4 = reinterpret_cast<const floatx4*>(u_in + size_t(t) * E * 6 * NP);
 #pragma unroll
-      for (int r = 0; r < CPT; ++r) pu[r] = s4[min(tid + r * NTH, TW4 - 1)];
+    for (int r = 0; r < CPT; ++r) pu[r] = u4[min(size_t(t) * TW4 + min(tid + r * NTH, TW4 - 1), chunk_last)];
 #pragma unroll
-      for (int r = 0; r < GPT; ++r) pg[r] = geo[size_t(t) * GW + min(tid + r * NTH, GW - 1)];
-      if (MAT) {
-        const int q = min(tid, 2 * E - 1);
-        pm = mat[(size_t(t) * E + q / 2) * dgh::kMatStride + (q & 1)];
-        const int qw = min(tid, 16 * E - 1);   // word qw % 16 of the face weights of element qw / 16
-        pw = mat[(size_t(t) * E + qw / 16) * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
-      }
+    for (int r = 0; r < GPT; ++r)
+      pg[r] = geo[min(size_t(t) * GW + min(tid + r * NTH, GW - 1), size_t(K) * G - 1)];
+    if (MAT) {
+      const int q = min(tid, 2 * E - 1);
+      const size_t e = min(size_t(t) * E + q / 2, size_t(K) - 1);
+      pm = mat[e * dgh::kMatStride + (q & 1)];
+      const int qw = min(tid, 16 * E - 1);   // word qw % 16 of the face weights of element qw / 16
+      const size_t ew = min(size_t(t) * E + qw / 16, size_t(K) - 1);
+      pw = mat[ew * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
     }
     pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
   };
@@ -828,6 +831,8 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
     const int nel = min(E, K - base);
     const bool full = nel == E;
     const size_t tb = size_t(base) * 6 * NP;
+    const bool more = tile + nwg < tend;
+    const int nxt = more ? tile + nwg : tile;
 
     if (full) {
 #pragma unroll
@@ -917,12 +922,12 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
       }
     }
     __syncthreads();
-    if (STAGE && full) {
+    if (STAGE) {
 #pragma unroll
       for (int r = 0; r < CPT; ++r)
-        rs4[r] = reinterpret_cast<const floatx4*>(res + tb)[min(tid + r * NTH, TW4 - 1)];
+        rs4[r] = reinterpret_cast<const floatx4*>(res)[min(size_t(tile) * TW4 + min(tid + r * NTH, TW4 - 1), chunk_last)];
     }
-    if (tile + nwg < tend) prefetch(tile + nwg);
+    prefetch(nxt);
 
     // ---- contraction: this wave's column tile against the three row tiles. Row tile t holds
     // rows 16 t + li, row = f E + e (two fields of 8 elements).
@@ -1010,7 +1015,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         }
       }
     }
-    if (D::AHEAD && tile + nwg < tend) gather(tile + nwg, fcb[par ^ 1]);
+    if (D::AHEAD) gather(nxt, fcb[more ? par ^ 1 : par]);
     __syncthreads();   // flux rows are read: reuse them for the staging
 
     // ---- stage the right-hand side [e][f][n]: lane (li, g4), register i = row 16 t + 4 g4 + i,
