@@ -412,6 +412,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     floatx4 rs[CPC];
 
+    // Issue priority (per wave): the two workgroups on a CU interleave their phases on each
+    // SIMD; the wave in its contraction is served first so that the matrix pipe stays fed,
+    // then a wave in its flux phase, which the contraction waits for; the loads, staging and
+    // write-out fill the gaps.
+    __builtin_amdgcn_s_setprio(2);
     // ---- face fluxes from the exterior traces gathered during the previous tile
     const int32_t* fc = fcb[par];
     {
@@ -479,6 +484,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         rs[j] = reinterpret_cast<const floatx4*>(res)[min(size_t(tile) * TC + min(tid + j * kThreads, TC - 1), chunk_last)];
     }
 
+    __builtin_amdgcn_s_setprio(3);
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
     // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
     // The tail columns accumulate in tacc (kept by the waves of column tile 0).
@@ -600,6 +606,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // tail: sum the partial results of the four k-groups (lanes li, li + 16, li + 32, li + 48)
     if (TAIL > 0) {
 #pragma unroll
@@ -929,6 +936,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
     }
     prefetch(nxt);
 
+    __builtin_amdgcn_s_setprio(3);   // contraction first on the SIMD, as in the kernel above
     // ---- contraction: this wave's column tile against the three row tiles. Row tile t holds
     // rows 16 t + li, row = f E + e (two fields of 8 elements).
     floatx4 acc[RT];
@@ -1015,6 +1023,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (D::AHEAD) gather(nxt, fcb[more ? par ^ 1 : par]);
     __syncthreads();   // flux rows are read: reuse them for the staging
 
