@@ -242,7 +242,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // MAT: heterogeneous medium. 1/eps and 1/mu of the tile's elements ride in the unused last
 // words of each element row of the padded tile (up_s) and scale the operand coefficients;
-// the face weights (material record) are read with the neighbour traces.
+// the face weights of the material records are prefetched with the tile into LDS (wmat).
 template <int N, bool STAGE, bool MAT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void mfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
@@ -252,9 +252,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   using D = MDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
                 NF = D::NF, KV = D::KV, KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT,
-                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, FIT = D::FIT,
-                PC = D::PC, LAST = D::LAST, TC = D::TC, CPC = D::CPC, VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF,
-                NQ = D::NQ;
+                TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, FIT = D::FIT, PC = D::PC,
+                LAST = D::LAST, TC = D::TC, CPC = D::CPC, VB = D::VB, VR = D::VR, QV = D::QV,
+                QF = D::QF, NQ = D::NQ;
   constexpr int G = dgh::kGeoStride;
   constexpr int GW = E * G;                                   // words of geometry per tile
   constexpr int GPT = (GW + kThreads - 1) / kThreads;
@@ -263,8 +263,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   __shared__ __align__(16) float gl[D::ROWS * RSL];   // Fscale/2 * flux [f E + e][fj]; later staging
   __shared__ __align__(16) float bfs[NT * KS * 64];   // operator fragments
   __shared__ __align__(16) float tops[TAIL > 0 ? KS * 16 : 4];  // tail operator fragments
-  __shared__ float gt[GW];
-  __shared__ __align__(16) float wmat[MAT ? E * 4 * dgh::kMatFace : 4];   // MAT: face weights [e][f][A B C D]                            // geometric records of the tile
+  __shared__ float gt[GW];                            // geometric records of the tile
+  __shared__ __align__(16) float wmat[MAT ? E * 4 * dgh::kMatFace : 4];   // MAT: [e][f][A B C D]
   __shared__ int32_t fcb[2][E * 4];                   // face records: this tile, the next
   __shared__ uint8_t nbr_s[96 * NFP];                 // neighbour node table
   __shared__ uint8_t fm_s[4 * NFP];                   // face node lists
@@ -306,15 +306,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int q = tid; q < 4 * NFP; q += kThreads) fm_s[q] = uint8_t(fmask[q]);
   if (TAIL > 0)
     for (int q = tid; q < KS * 16; q += kThreads) tops[q] = opf[NT * KS * 64 + q];
-  // the pad columns of up_s are never written again
+  // up_s starts zeroed, so that the rows past the elements of a ragged tile hold finite values
   for (int q = tid; q < E * ES; q += kThreads) up_s[q] = 0.f;
   __syncthreads();
 
   // Prefetch registers: fields and geometry of the next tile, the neighbour traces of its
-  // face nodes, and the face records of the tile after it. Every thread loads every slot
-  // (indices clamped): exec-masked loads make the compiler wait for all outstanding loads
-  // before reusing their registers. In the material variant the face-node slot of this
-  // thread is made opaque so that its index arithmetic is not hoisted out of the tile loop.
+  // face nodes, and the face records of the tile after it. In the material variant the
+  // face-node slot of this thread is made opaque so that its index arithmetic is not hoisted
+  // out of the tile loop.
   int tq = tid;
   if (MAT) asm volatile("" : "+v"(tq));
   floatx4 pu[CPC];
@@ -322,9 +321,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   float nup[FIT][6];   // exterior traces u+ of the face nodes tq + r kThreads (all six fields)
   int32_t pf = 0;
   float pm = 0.f, pw = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
-  // Every prefetch load is issued on every path, its index clamped into its array (a ragged
-  // or missing next tile loads values that are not used): the compiler's wait counts then
-  // hold on every path, so a wait for one load never falls back to waiting for all of them.
+  // Every thread loads every slot, on every path, its index clamped into its array (a ragged
+  // or missing next tile loads values that are not used): an exec-masked load makes the
+  // compiler wait for all outstanding loads before reusing its registers, and a load skipped
+  // on some path makes a later wait for one load fall back to waiting for all of them.
   const size_t fc_last = size_t(K) * 4 - 1;
   const size_t chunk_last = size_t(K) * 6 * NPP / 4 - 1;
   const floatx4* u4 = reinterpret_cast<const floatx4*>(u_in);
@@ -868,6 +868,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 
     floatx4 rs4[CPT];
 
+    __builtin_amdgcn_s_setprio(2);   // issue priorities as in the kernel above
     // ---- face fluxes (as in the kernel above)
     const int32_t* fc = fcb[par];
     if (!D::AHEAD) gather(tile, fc);
@@ -936,7 +937,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
     }
     prefetch(nxt);
 
-    __builtin_amdgcn_s_setprio(3);   // contraction first on the SIMD, as in the kernel above
+    __builtin_amdgcn_s_setprio(3);
     // ---- contraction: this wave's column tile against the three row tiles. Row tile t holds
     // rows 16 t + li, row = f E + e (two fields of 8 elements).
     floatx4 acc[RT];
