@@ -212,6 +212,9 @@ struct MDims {
   static constexpr int LAST = Np - 4 * (PC - 1);     // field words in the last chunk of a row
   static constexpr int TC = 6 * E * PC;              // chunks per tile
   static constexpr int CPC = (TC + kThreads - 1) / kThreads;   // chunks per thread
+  // per-wave issue priorities (contraction first); at N = 3 the stage is bound by its memory
+  // phases, and serving the short contraction first slows it (313 against 286 us per stage)
+  static constexpr bool PRIO = N >= 4;
   static_assert(ES % 4 == 0, "element rows of the padded tile are 16-byte aligned");
   static constexpr int NF = (Nf4 + 15) / 16 * 16;    // face block, padded
   static constexpr int RSL = NF + 4;                 // flux row stride (= 4 mod 8)
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     // SIMD; the wave in its contraction is served first so that the matrix pipe stays fed,
     // then a wave in its flux phase, which the contraction waits for; the loads, staging and
     // write-out fill the gaps.
-    __builtin_amdgcn_s_setprio(2);
+    if (D::PRIO) __builtin_amdgcn_s_setprio(2);
     // ---- face fluxes from the exterior traces gathered during the previous tile
     const int32_t* fc = fcb[par];
     {
@@ -484,10 +487,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         rs[j] = reinterpret_cast<const floatx4*>(res)[min(size_t(tile) * TC + min(tid + j * kThreads, TC - 1), chunk_last)];
     }
 
-    __builtin_amdgcn_s_setprio(3);
+    if (D::PRIO) __builtin_amdgcn_s_setprio(3);
     // ---- main contraction: tiles wave, wave + 4, ... (row tile = field, lane row = element li).
     // A wave with fewer than TPW tiles repeats its last one and drops the result (branch-free).
-    // The tail columns accumulate in tacc (kept by the waves of column tile 0).
+    // The tail columns accumulate in tacc on the waves of column tile 0 only (a wave-uniform
+    // condition: the other waves would drop them).
     floatx4 acc[TPW], tacc[TPW];
     {
       float pc[TPW][3], qc[TPW][3];   // operand = pc[mu] * V_c[j] + qc[mu] * V_b[j]
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
             // the 16x16x4 products of all tiles first, then the short tail products
 #pragma unroll
             for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], wv[s], acc[t], 0, 0, 0);
-            if (TAIL > 0)
+            if (TAIL > 0 && nt == 0)
 #pragma unroll
               for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[t], zv[s], tacc[t], 0, 0, 0);
           }
@@ -576,7 +580,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int t = 0; t < TPW; ++t) xs[t] = s == 0 ? xf[t].x : s == 1 ? xf[t].y : s == 2 ? xf[t].z : xf[t].w;
 #pragma unroll
           for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[t], wv[s], acc[t], 0, 0, 0);
-          if (TAIL > 0)
+          if (TAIL > 0 && nt == 0)
 #pragma unroll
             for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(xs[t], zv[s], tacc[t], 0, 0, 0);
         }
@@ -599,16 +603,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int t = 0; t < TPW; ++t) av[t] = pc[t][mu] * xc1[t] + qc[t][mu] * xb1[t];
 #pragma unroll
           for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], w, acc[t], 0, 0, 0);
-          if (TAIL > 0)
+          if (TAIL > 0 && nt == 0)
 #pragma unroll
             for (int t = 0; t < TPW; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[t], zs, tacc[t], 0, 0, 0);
         }
       }
     }
 
-    __builtin_amdgcn_s_setprio(0);
+    if (D::PRIO) __builtin_amdgcn_s_setprio(0);
     // tail: sum the partial results of the four k-groups (lanes li, li + 16, li + 32, li + 48)
-    if (TAIL > 0) {
+    if (TAIL > 0 && nt == 0) {
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
