@@ -38,6 +38,46 @@ constexpr bool contraction_order(int N) { return N >= 3 && N <= 6; }
 template <typename T, int N>
 constexpr int kRowStride = (sizeof(T) == 4 && contraction_order(N)) ? (Dims<N>::Np + 3) / 4 * 4 : Dims<N>::Np;
 
+// Jump u+ - u- at a face node (Sec. 6): a perfectly conducting wall mirrors the interior
+// state (E+ = -E-, H+ = H-), an absorbing face has zero exterior state, an interior face
+// takes the neighbour's trace p (six fields).
+template <typename T>
+__device__ __forceinline__ void face_jump(int code, const T (&m)[6], const T (&p)[6], T (&d)[6]) {
+  const bool inner = code >= 0, pec = code == dgh::kFacePec;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {   // selects, no branches
+    const T wall = pec ? (c < 3 ? T(-2) * m[c] : T(0)) : -m[c];
+    d[c] = inner ? p[c] - m[c] : wall;
+  }
+}
+
+// Upwind flux of Sec. 6 at a face node with unit normal n and jump d = (dE, dH), written to
+// o[0], o[os], ..., o[5 os] already scaled: in vacuum by hs = Fscale / 2; in a medium by the
+// impedance weights w = (A, B, C, D) of the material record, which fold in Fscale, 1/eps, 1/mu.
+template <typename T>
+__device__ __forceinline__ void upwind_flux(bool medium, T nx, T ny, T nz, T hs, const T (&w)[4],
+                                            const T (&d)[6], T* o, int os) {
+  const T dEx = d[0], dEy = d[1], dEz = d[2], dHx = d[3], dHy = d[4], dHz = d[5];
+  const T ndE = nx * dEx + ny * dEy + nz * dEz;
+  const T ndH = nx * dHx + ny * dHy + nz * dHz;
+  if (medium) {
+    const T A = w[0], B = w[1], C = w[2], Dd = w[3];
+    o[0 * os] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
+    o[1 * os] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
+    o[2 * os] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
+    o[3 * os] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
+    o[4 * os] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
+    o[5 * os] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
+  } else {
+    o[0 * os] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
+    o[1 * os] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
+    o[2 * os] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
+    o[3 * os] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
+    o[4 * os] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
+    o[5 * os] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+  }
+}
+
 // Workgroups are dispatched round-robin over the XCDs; give every XCD a contiguous range of
 // tiles so that neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
@@ -76,43 +116,22 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
     const T* g = geo + size_t(elem) * G + dgh::kGeoNormal + 4 * f;
     const T nx = g[0], ny = g[1], nz = g[2], hs = T(0.5) * g[3];
     const T* um = us + e * 6 * NP + fmask[f * NFP + j];
-    const T Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
-    T dEx, dEy, dEz, dHx, dHy, dHz;
+    T m[6], p[6] = {}, d[6], w[4] = {};
+    for (int c = 0; c < 6; ++c) m[c] = um[c * NP];
     const int code = fcode[size_t(elem) * 4 + f];
-    if (code == dgh::kFacePec) {   // perfectly conducting wall: E+ = -E-, H+ = H-
-      dEx = T(-2) * Ex, dEy = T(-2) * Ey, dEz = T(-2) * Ez;
-      dHx = dHy = dHz = T(0);
-    } else if (code < 0) {         // absorbing face: zero exterior state
-      dEx = -Ex, dEy = -Ey, dEz = -Ez;
-      dHx = -Hx, dHy = -Hy, dHz = -Hz;
-    } else {
+    if (code >= 0) {
       const int nb = code >> 5, o = (code >> 2) & 7, f2 = code & 3;
       const int nn = nbrnode[((f * 4 + f2) * 6 + o) * NFP + j];
       const int le = nb - base;
       const T* up = (le >= 0 && le < nel) ? us + le * 6 * NP + nn : u_in + size_t(nb) * 6 * NP + nn;
-      dEx = up[0] - Ex, dEy = up[NP] - Ey, dEz = up[2 * NP] - Ez;
-      dHx = up[3 * NP] - Hx, dHy = up[4 * NP] - Hy, dHz = up[5 * NP] - Hz;
+      for (int c = 0; c < 6; ++c) p[c] = up[c * NP];
     }
-    const T ndE = nx * dEx + ny * dEy + nz * dEz;
-    const T ndH = nx * dHx + ny * dHy + nz * dHz;
-    T* o = fl + e * 6 * NF4 + fj;
+    face_jump(code, m, p, d);
     if (mat) {
-      const T* w = mat + size_t(elem) * dgh::kMatStride + dgh::kMatFace + 4 * f;
-      const T A = w[0], B = w[1], C = w[2], Dd = w[3];
-      o[0 * NF4] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
-      o[1 * NF4] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
-      o[2 * NF4] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
-      o[3 * NF4] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
-      o[4 * NF4] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
-      o[5 * NF4] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
-      continue;
+      const T* mw = mat + size_t(elem) * dgh::kMatStride + dgh::kMatFace + 4 * f;
+      for (int c = 0; c < 4; ++c) w[c] = mw[c];
     }
-    o[0 * NF4] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
-    o[1 * NF4] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
-    o[2 * NF4] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
-    o[3 * NF4] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
-    o[4 * NF4] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
-    o[5 * NF4] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
+    upwind_flux(mat != nullptr, nx, ny, nz, hs, w, d, fl + e * 6 * NF4 + fj, NF4);
   }
   __syncthreads();
 
@@ -254,7 +273,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
   using D = MDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
-                NF = D::NF, KV = D::KV, KD = D::KD, KS = D::KS, RSL = D::RSL, NT = D::NT,
+                NF = D::NF, KS = D::KS, RSL = D::RSL, NT = D::NT,
                 TAIL = D::TAIL, TILES = D::TILES, TPW = D::TPW, FIT = D::FIT, PC = D::PC,
                 LAST = D::LAST, TC = D::TC, CPC = D::CPC, VB = D::VB, VR = D::VR, QV = D::QV,
                 QF = D::QF, NQ = D::NQ;
@@ -433,10 +452,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         }
       }
       // face columns NF4 .. NF-1 of every row are padding: keep them zero
-      for (int q = tid; q < D::ROWS * (NF - NF4); q += kThreads) {
-        const int row = q / (NF - NF4);
-        gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
-      }
+      if constexpr (NF > NF4)
+        for (int q = tid; q < D::ROWS * (NF - NF4); q += kThreads) {
+          const int row = q / (NF - NF4);
+          gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
+        }
 #pragma unroll
       for (int r = 0; r < FIT; ++r) {
         const int q = tq + r * kThreads;
@@ -445,38 +465,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
           const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
           const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
           const float* um = up_s + e * ES + fm_s[f * NFP + j];
-          const float Ex = um[0], Ey = um[NPP], Ez = um[2 * NPP], Hx = um[3 * NPP], Hy = um[4 * NPP], Hz = um[5 * NPP];
-          float dEx, dEy, dEz, dHx, dHy, dHz;
-          const int code = fc[e * 4 + f];
-          if (code == dgh::kFacePec) {   // perfectly conducting wall: E+ = -E-, H+ = H-
-            dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
-            dHx = dHy = dHz = 0.f;
-          } else if (code < 0) {         // absorbing face: zero exterior state
-            dEx = -Ex, dEy = -Ey, dEz = -Ez;
-            dHx = -Hx, dHy = -Hy, dHz = -Hz;
-          } else {
-            dEx = nup[r][0] - Ex, dEy = nup[r][1] - Ey, dEz = nup[r][2] - Ez;
-            dHx = nup[r][3] - Hx, dHy = nup[r][4] - Hy, dHz = nup[r][5] - Hz;
-          }
-          const float ndE = nx * dEx + ny * dEy + nz * dEz;
-          const float ndH = nx * dHx + ny * dHy + nz * dHz;
-          float* o = gl + e * RSL + fj;
-          if (MAT) {
-            const float A = wm[r].x, B = wm[r].y, C = wm[r].z, Dd = wm[r].w;
-            o[0 * E * RSL] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
-            o[1 * E * RSL] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
-            o[2 * E * RSL] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
-            o[3 * E * RSL] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
-            o[4 * E * RSL] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
-            o[5 * E * RSL] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
-          } else {
-            o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
-            o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
-            o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
-            o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
-            o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
-            o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
-          }
+          float m[6], d[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) m[c] = um[c * NPP];
+          face_jump(fc[e * 4 + f], m, nup[r], d);
+          const float w[4] = {wm[r].x, wm[r].y, wm[r].z, wm[r].w};
+          upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
         }
       }
     }
@@ -740,7 +734,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
     const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
   using D = HDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
-                NF = D::NF, KS = D::KS, RSL = D::RSL, RT = D::RT, FIT = D::FIT, TW = D::TW,
+                NF = D::NF, KS = D::KS, RSL = D::RSL, RT = D::RT, FIT = D::FIT,
                 TW4 = D::TW4, CPT = D::CPT, VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF,
                 NQ = D::NQ, NTH = D::THREADS;
   constexpr int G = dgh::kGeoStride;
@@ -886,10 +880,11 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
           wm[r] = *reinterpret_cast<const floatx4*>(wmat + 16 * e + 4 * f);
         }
       }
-      for (int q = tid; q < D::ROWS * (NF - NF4); q += NTH) {
-        const int row = q / (NF - NF4);
-        gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
-      }
+      if constexpr (NF > NF4)
+        for (int q = tid; q < D::ROWS * (NF - NF4); q += NTH) {
+          const int row = q / (NF - NF4);
+          gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
+        }
 #pragma unroll
       for (int r = 0; r < FIT; ++r) {
         const int q = tq + r * NTH;
@@ -898,38 +893,12 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
           const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
           const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
           const float* um = up_s + e * ES + fm_s[f * NFP + j];
-          const float Ex = um[0], Ey = um[NP], Ez = um[2 * NP], Hx = um[3 * NP], Hy = um[4 * NP], Hz = um[5 * NP];
-          float dEx, dEy, dEz, dHx, dHy, dHz;
-          const int code = fc[e * 4 + f];
-          if (code == dgh::kFacePec) {
-            dEx = -2.f * Ex, dEy = -2.f * Ey, dEz = -2.f * Ez;
-            dHx = dHy = dHz = 0.f;
-          } else if (code < 0) {
-            dEx = -Ex, dEy = -Ey, dEz = -Ez;
-            dHx = -Hx, dHy = -Hy, dHz = -Hz;
-          } else {
-            dEx = nup[r][0] - Ex, dEy = nup[r][1] - Ey, dEz = nup[r][2] - Ez;
-            dHx = nup[r][3] - Hx, dHy = nup[r][4] - Hy, dHz = nup[r][5] - Hz;
-          }
-          const float ndE = nx * dEx + ny * dEy + nz * dEz;
-          const float ndH = nx * dHx + ny * dHy + nz * dHz;
-          float* o = gl + e * RSL + fj;
-          if (MAT) {
-            const float A = wm[r].x, B = wm[r].y, C = wm[r].z, Dd = wm[r].w;
-            o[0 * E * RSL] = A * (ny * dHz - nz * dHy) + B * (dEx - ndE * nx);
-            o[1 * E * RSL] = A * (nz * dHx - nx * dHz) + B * (dEy - ndE * ny);
-            o[2 * E * RSL] = A * (nx * dHy - ny * dHx) + B * (dEz - ndE * nz);
-            o[3 * E * RSL] = C * (nz * dEy - ny * dEz) + Dd * (dHx - ndH * nx);
-            o[4 * E * RSL] = C * (nx * dEz - nz * dEx) + Dd * (dHy - ndH * ny);
-            o[5 * E * RSL] = C * (ny * dEx - nx * dEy) + Dd * (dHz - ndH * nz);
-          } else {
-            o[0 * E * RSL] = hs * (ny * dHz - nz * dHy + dEx - ndE * nx);
-            o[1 * E * RSL] = hs * (nz * dHx - nx * dHz + dEy - ndE * ny);
-            o[2 * E * RSL] = hs * (nx * dHy - ny * dHx + dEz - ndE * nz);
-            o[3 * E * RSL] = hs * (nz * dEy - ny * dEz + dHx - ndH * nx);
-            o[4 * E * RSL] = hs * (nx * dEz - nz * dEx + dHy - ndH * ny);
-            o[5 * E * RSL] = hs * (ny * dEx - nx * dEy + dHz - ndH * nz);
-          }
+          float m[6], d[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) m[c] = um[c * NP];
+          face_jump(fc[e * 4 + f], m, nup[r], d);
+          const float w[4] = {wm[r].x, wm[r].y, wm[r].z, wm[r].w};
+          upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
         }
       }
     }
