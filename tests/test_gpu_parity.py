@@ -182,6 +182,31 @@ def test_degenerate_meshes_single_and_two_tets(N):
 
 
 @pytest.mark.parametrize("N", [3, 4, 5, 6])
+def test_fp32_field_round_trip_and_energy(N):
+    """The FP32 internal layout (rows padded to a multiple of 4 nodes at N = 4, pad words kept
+    zero): fields come back bitwise through the host and the device paths, and the energy
+    equals the oracle's for the same FP32 values, in vacuum and in a medium."""
+    import torch
+    v, e, m, u0 = problem(N, 3, jitter=0.15, permute=True)
+    u32 = rounded(u0, "f32")
+    eps, mu = dginputs.random_materials(e.shape[0])
+    for kw in ({}, dict(eps=eps, mu=mu)):
+        say(f"case: N={N} K={m.K} f32 {'medium' if kw else 'vacuum'} round trip + energy")
+        s = P.Solver(v, e, N, "f32", reorder=1, **kw)
+        s.set_fields(u32)
+        assert np.array_equal(s.get_fields(), u32)
+        t = torch.from_numpy(u32.astype(np.float32)).cuda()
+        s.set_fields(t)
+        back = torch.empty_like(t)
+        s.get_fields(back)
+        torch.cuda.synchronize()
+        assert torch.equal(back, t)
+        eo = W.energy(m, u32, **kw)
+        assert abs(s.energy() - eo) <= 1e-6 * eo
+        s.free()
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 6])
 def test_fp32_meshes_smaller_than_a_tile(N):
     """The FP32 contraction kernels on 1, 2 and 6 elements (one ragged tile, shorter than a
     tile of the field arrays, so every clamped prefetch index lands inside the arrays): the
