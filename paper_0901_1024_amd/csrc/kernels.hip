@@ -234,6 +234,9 @@ struct MDims {
   // per-wave issue priorities (contraction first); at N = 3 the stage is bound by its memory
   // phases, and serving the short contraction first slows it (313 against 286 us per stage)
   static constexpr bool PRIO = N >= 4;
+  // waves per SIMD the register budget is set for: four at N = 3 (128 VGPRs, a few spills, four
+  // workgroups per CU: 274 against 289 us per stage), two at N = 4
+  static constexpr int WPE = N == 3 ? 4 : 2;
   static_assert(ES % 4 == 0, "element rows of the padded tile are 16-byte aligned");
   static constexpr int NF = (Nf4 + 15) / 16 * 16;    // face block, padded
   static constexpr int RSL = NF + 4;                 // flux row stride (= 4 mod 8)
@@ -266,7 +269,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // words of each element row of the padded tile (up_s) and scale the operand coefficients;
 // the face weights of the material records are prefetched with the tile into LDS (wmat).
 template <int N, bool STAGE, bool MAT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void mfma_stage_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<N>::WPE, MDims<N>::WPE))) void mfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
     const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
