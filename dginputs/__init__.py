@@ -9,7 +9,8 @@ into n^3 small cubes, each cut into the six Kuhn tetrahedra sharing the main dia
 perfectly conducting cavity test of Sec. 6 is represented by the (1,1,0) TM mode of the unit
 cube, whose closed form is given by `cavity_tm110`.
 
-Seeds (NumPy PCG64): jitter 1, element permutation 2, smooth fields 3, batch 4, arrivals 5.
+Seeds (NumPy PCG64): jitter 1, element permutation 2, smooth fields 3, batch 4, arrivals 5,
+materials 6, local vertex order 7.
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ SEED_FIELDS = 3
 SEED_BATCH = 4
 SEED_ARRIVALS = 5
 SEED_MATERIAL = 6
+SEED_SHUFFLE = 7
 
 # Vertex triples of the four faces of a tetrahedron (v1..v4 = 0..3), the numbering of the
 # library interface: F1 = (v1,v2,v3), F2 = (v1,v2,v4), F3 = (v2,v3,v4), F4 = (v1,v3,v4).
@@ -43,14 +45,18 @@ def rng(seed: int) -> np.random.Generator:
 
 def kuhn_cube(n: int, jitter: float = 0.0, permute: bool = False,
               seed_jitter: int = SEED_JITTER, seed_perm: int = SEED_PERM,
-              nx: int | None = None, ny: int | None = None, nz: int | None = None):
+              nx: int | None = None, ny: int | None = None, nz: int | None = None,
+              shuffle: bool = False, seed_shuffle: int = SEED_SHUFFLE):
     """Unit-cube tetrahedral mesh of 6*nx*ny*nz Kuhn tetrahedra.
 
     Returns (vxyz, etov): vxyz is (nverts, 3) float64, etov is (K, 4) int32, 0-based.
     Vertex id = (iz*(ny+1) + iy)*(nx+1) + ix at (ix/nx, iy/ny, iz/nz).
     Element id = ((cz*ny + cy)*nx + cx)*6 + p before the optional permutation.
     `jitter` moves every interior vertex by U(-jitter*h, jitter*h) per coordinate, with h the
-    cell width along that axis; `permute` shuffles the element order (Fisher-Yates).
+    cell width along that axis; `permute` shuffles the element order (Fisher-Yates);
+    `shuffle` lists the four vertices of every element in a random order of its own (half of
+    the elements then come out negatively oriented), so that neighbouring elements meet in
+    every relative face numbering and vertex rotation a conforming mesh allows.
     """
     nx = n if nx is None else nx
     ny = n if ny is None else ny
@@ -95,6 +101,10 @@ def kuhn_cube(n: int, jitter: float = 0.0, permute: bool = False,
         g = rng(seed_perm)
         perm = g.permutation(etov.shape[0])
         etov = etov[perm]
+    if shuffle:
+        g = rng(seed_shuffle)
+        order = np.argsort(g.random(etov.shape), axis=1)
+        etov = np.take_along_axis(etov, order, axis=1)
     return vxyz, etov.astype(np.int32)
 
 

@@ -146,19 +146,36 @@ def rhs(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
     return _assemble(mesh.ref, vol, flux, mesh.Fscale, e, m)
 
 
-def rhs_at(mesh: Mesh, u, elems, alpha=1.0):
-    """The same right-hand side (vacuum) evaluated only at the elements `elems`: (6, len, Np).
-    Face maps are computed for those elements only, so the mesh may be built with
-    compute_maps=False."""
+def rhs_at(mesh: Mesh, u, elems, alpha=1.0, eps=None, mu=None, absorb=None):
+    """The same right-hand side evaluated only at the elements `elems`: (6, len, Np). Face
+    maps are computed for those elements only, so the mesh may be built with
+    compute_maps=False. eps, mu (per element, None = 1) and absorb ((K, 4) absorbing-face
+    flags) as in rhs()."""
     from .mesh import face_maps
     elems = np.asarray(elems, dtype=np.int64)
     ref = mesh.ref
     K, Np = u.shape[1], u.shape[2]
     vol = _curl_term(ref, mesh.G[elems], u[:, elems, :])
     vM, vP = face_maps(mesh.x, mesh.EToE, mesh.EToF, ref.Fmask, elems)
+    absorb = _check_absorb(mesh, absorb)
     flux = _flux_terms(u.reshape(6, K * Np), vM, vP, mesh.boundary[elems], mesh.n[elems], alpha,
-                       _impedances(mesh, elems, None, None))
-    return _assemble(ref, vol, flux, mesh.Fscale[elems], None, None)
+                       _impedances(mesh, elems, eps, mu), None if absorb is None else absorb[elems])
+    e = None if eps is None else np.asarray(eps, dtype=np.float64)[elems]
+    m = None if mu is None else np.asarray(mu, dtype=np.float64)[elems]
+    return _assemble(ref, vol, flux, mesh.Fscale[elems], e, m)
+
+
+def rhs_range(mesh: Mesh, u, k0, k1, alpha=1.0):
+    """The right-hand side (vacuum) at elements k0 .. k1-1 of a mesh built with its face maps,
+    (6, k1 - k0, Np): the same arithmetic as rhs() on a contiguous range of elements, so that
+    disjoint ranges can be evaluated on separate host cores."""
+    sl = slice(k0, k1)
+    ref = mesh.ref
+    K, Np = u.shape[1], u.shape[2]
+    vol = _curl_term(ref, mesh.G[sl], u[:, sl, :])
+    flux = _flux_terms(u.reshape(6, K * Np), mesh.vmapM[sl], mesh.vmapP[sl], mesh.boundary[sl], mesh.n[sl],
+                       alpha, _impedances(mesh, np.arange(k0, k1), None, None))
+    return _assemble(ref, vol, flux, mesh.Fscale[sl], None, None)
 
 
 def lsrk4_step(mesh: Mesh, u, dt, res=None, **kw):
@@ -180,7 +197,7 @@ def face_rings(mesh: Mesh, elems, depth):
     return rings
 
 
-def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0):
+def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0, **kw):
     """One LSRK4 step from res = 0, evaluated only where it is needed for `elems`.
 
     A stage's right-hand side at an element reads only that element and its face neighbours,
@@ -193,7 +210,7 @@ def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0):
     res = np.zeros_like(u)
     for i, (a, b) in enumerate(zip(RK4A, RK4B)):
         S = rings[4 - i]
-        r = rhs_at(mesh, u, S, alpha)
+        r = rhs_at(mesh, u, S, alpha, **kw)
         res[:, S] = a * res[:, S] + dt * r
         u[:, S] = u[:, S] + b * res[:, S]
     return u[:, np.asarray(elems, dtype=np.int64)]

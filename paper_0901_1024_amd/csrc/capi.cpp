@@ -110,10 +110,11 @@ struct dg_handle {
   bool own_ws = false;
   int cur = 0;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  double graph_dt = 0.0;
-  int graph_cur = -1;
+  // captured two-step graphs, one per parity of the ping-pong state (h->cur at capture), so
+  // that a solve after an odd number of steps replays rather than re-captures
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  double graph_dt[2] = {0.0, 0.0};
 
   bool f64() const { return prec == DG_F64; }
   void* at(size_t off) const { return ws + off; }
@@ -131,12 +132,15 @@ struct dg_handle {
     o.opfrag = lay.opcat_bytes ? at(lay.off_opcat) : nullptr;
     return o;
   }
-  void drop_graph() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
-    graph_cur = -1;
+  void drop_graph(int p) {
+    if (gexec[p]) (void)hipGraphExecDestroy(gexec[p]);
+    if (graph[p]) (void)hipGraphDestroy(graph[p]);
+    gexec[p] = nullptr;
+    graph[p] = nullptr;
+  }
+  void drop_graphs() {
+    drop_graph(0);
+    drop_graph(1);
   }
 };
 
@@ -437,7 +441,7 @@ int dg_free(dg_handle* h) {
   if (!h) return DG_OK;
   if (h->device >= 0) {
     (void)hipSetDevice(h->device);
-    h->drop_graph();
+    h->drop_graphs();
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
   }
@@ -556,9 +560,10 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (nsteps >= 2) {
     // Two steps (ten stages) return the ping-pong state buffers to their starting roles, so
-    // one captured graph replays any even number of steps.
-    if (!h->gexec || h->graph_dt != dt || h->graph_cur != h->cur) {
-      h->drop_graph();
+    // one captured graph per starting parity replays any even number of steps.
+    const int p = h->cur;
+    if (!h->gexec[p] || h->graph_dt[p] != dt) {
+      h->drop_graph(p);
       const int saved = h->cur;
       HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
       int r1 = rk_step_launch(h, dt, h->cap_stream);
@@ -571,12 +576,11 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
         return r2;
       }
       if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      h->graph = g;
-      HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
-      h->graph_dt = dt;
-      h->graph_cur = h->cur;
+      h->graph[p] = g;
+      HIP_TRY(hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0));
+      h->graph_dt[p] = dt;
     }
-    for (int64_t i = 0; i + 1 < nsteps; i += 2) HIP_TRY(hipGraphLaunch(h->gexec, s));
+    for (int64_t i = 0; i + 1 < nsteps; i += 2) HIP_TRY(hipGraphLaunch(h->gexec[p], s));
   }
   if (nsteps % 2) return rk_step_launch(h, dt, s);
   return DG_OK;

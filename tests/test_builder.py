@@ -53,6 +53,23 @@ def test_builder_maps_are_bit_identical_to_oracle(N, n, jitter, permute):
     assert abs(s.stable_dt(0.5) - dt_o) <= 1e-14 * dt_o
 
 
+@pytest.mark.parametrize("N", range(1, 8))
+def test_builder_maps_on_shuffled_vertex_order(N):
+    """Every element lists its vertices in a random order of its own (half come out negatively
+    oriented), so the mesh reaches all 48 (face, neighbour face, vertex rotation) combinations
+    that conforming tetrahedra allow, i.e. every row of the neighbour-node table that a
+    kernel can index: the combinatorial maps still equal the oracle's coordinate maps."""
+    from gpu_helpers import face_combos
+    v, e = dginputs.kuhn_cube(3, jitter=0.15, permute=True, shuffle=True)
+    assert len(face_combos(v, e)) == 48
+    s = P.Solver(v, e, N, device=-1)
+    m = Mm.Mesh(v, e, R.ref_element(N))
+    vM, vP = s.get_maps()
+    assert np.array_equal(vM, m.vmapM)
+    assert np.array_equal(vP, m.vmapP)
+    assert np.max(np.abs(s.nodes() - m.x)) <= 1e-14
+
+
 def test_builder_orients_negative_elements_like_the_oracle():
     v, e = dginputs.kuhn_cube(2, jitter=0.1)
     e = e.copy()

@@ -131,3 +131,20 @@ def test_uniform_medium_cavity_converges():
         errs.append(err)
     rate = math.log(errs[-2] / errs[-1]) / math.log(2.0)
     assert rate >= N + 0.5
+
+
+def test_sampled_rhs_and_step_equal_the_full_ones_in_a_medium():
+    """The sampled forms (used at full mesh sizes) with per-element eps, mu and absorbing faces
+    equal the full right-hand side and step bitwise at the sampled elements."""
+    v, e = dginputs.kuhn_cube(3, jitter=0.15, permute=True, shuffle=True)
+    m = Mm.Mesh(v, e, R.ref_element(3))
+    eps, mu = dginputs.random_materials(m.K, seed=21)
+    absorb = dginputs.faces_on_plane(v, m.etov, 2, 1.0).astype(bool)
+    assert absorb.any()
+    kw = dict(eps=eps, mu=mu, absorb=absorb)
+    u = dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), *m.x)
+    idx = np.unique(np.concatenate([np.nonzero(absorb.any(1))[0][:3], [0, 7, 50, m.K - 1]]))
+    assert np.array_equal(W.rhs_at(m, u, idx, **kw), W.rhs(m, u, **kw)[:, idx])
+    dt = W.stable_dt(m)
+    full, _ = W.lsrk4_step(m, u, dt, **kw)
+    assert np.array_equal(W.lsrk4_step_at(m, u, dt, idx, **kw), full[:, idx])

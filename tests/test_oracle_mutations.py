@@ -139,3 +139,55 @@ def test_planted_material_mistake_is_caught(monkeypatch, name, target, replaceme
     monkeypatch.setattr(W, target, replacement)
     A = assemble(mo, eps=EPS, mu=MU, absorb=absorb)
     assert np.linalg.norm(A - A_bf) > 1e-3 * np.linalg.norm(A_bf), name
+
+
+# ---------------------------------------------------------------------------------------
+# discrete energy and L2 norm
+
+from test_oracle_energy import energy_pins_hold  # noqa: E402
+
+
+def _energy_without_half(mesh, u, eps=None, mu=None):
+    return 2.0 * W.energy(mesh, u, eps, mu)
+
+
+def _energy_without_J(mesh, u, eps=None, mu=None):
+    saved = mesh.J
+    mesh.J = np.ones_like(saved)
+    try:
+        return W.energy(mesh, u, eps, mu)
+    finally:
+        mesh.J = saved
+
+
+def _energy_eps_mu_exchanged(mesh, u, eps=None, mu=None):
+    return W.energy(mesh, u, mu, eps)
+
+
+def _norm_without_J(mesh, u, uref):
+    saved = mesh.J
+    mesh.J = np.ones_like(saved)
+    try:
+        return W.l2_error(mesh, u, uref)
+    finally:
+        mesh.J = saved
+
+
+def _norm_squared(mesh, u, uref):
+    a, b = W.l2_error(mesh, u, uref)
+    return a * a, b * b
+
+
+def test_unmutated_energy_and_norm_hold():
+    assert energy_pins_hold(W.energy, W.l2_error)
+
+
+@pytest.mark.parametrize("name,energy_fn,l2_fn", [
+    ("energy without the factor 1/2", _energy_without_half, W.l2_error),
+    ("energy without the Jacobian", _energy_without_J, W.l2_error),
+    ("eps and mu weights exchanged", _energy_eps_mu_exchanged, W.l2_error),
+    ("norm without the Jacobian", W.energy, _norm_without_J),
+    ("norm squared instead of its root", W.energy, _norm_squared),
+])
+def test_planted_energy_or_norm_mistake_is_caught(name, energy_fn, l2_fn):
+    assert not energy_pins_hold(energy_fn, l2_fn), name
