@@ -141,6 +141,18 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream);
  * Synchronises `stream`. */
 int dg_energy(const dg_handle* h, double* energy, void* stream);
 
+/* The energy of dg_energy, computed without allocating anything and without synchronising:
+ * for callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). The result (one double) is written to the device
+ * pointer `energy_dev` on `stream`. The per-block partial sums go to a static device array of
+ * the library (512 KiB on each device, set up by dg_setup), so K is limited to 4,194,304
+ * elements (larger: DG_E_ARG, use dg_energy). Every call on a device shares that array: calls
+ * that overlap on one device (other streams, other threads) race and must be ordered by the
+ * caller. Nothing in the array needs to start at zero (each call writes every partial it
+ * reads). The summation order differs from dg_energy's (tree against sequential), so the two
+ * agree to rounding. */
+int dg_energy_noalloc(const dg_handle* h, double* energy_dev, void* stream);
+
 /* Time-step bound used by the tests and the benchmark: cfl * min over faces of 1/Fscale,
  * divided by N^2 (host-only). It assumes wave speed at most 1, i.e. eps * mu >= 1. */
 int dg_stable_dt(const dg_handle* h, double cfl, double* dt);

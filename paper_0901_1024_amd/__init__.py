@@ -24,7 +24,7 @@ _ERRS = {-1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_UNSUPPORTED", -4: "DG_E_OOM"
 # every symbol declared in include/dg.h
 EXPORTS = ["dg_setup_query", "dg_setup", "dg_free", "dg_last_error", "dg_info", "dg_nodes",
            "dg_get_maps", "dg_get_operators", "dg_set_fields", "dg_get_fields", "dg_rhs",
-           "dg_rk_step", "dg_solve", "dg_energy", "dg_stable_dt", "dg_setup_query_batch",
+           "dg_rk_step", "dg_solve", "dg_energy", "dg_energy_noalloc", "dg_stable_dt", "dg_setup_query_batch",
            "dg_setup_batch", "dg_batch_info", "dg_batch_stable_dt", "dg_set_batch_dt"]
 
 
@@ -82,6 +82,7 @@ def lib():
         L.dg_rk_step.argtypes = [vp, dbl, vp]
         L.dg_solve.argtypes = [vp, dbl, i64, vp]
         L.dg_energy.argtypes = [vp, ctypes.POINTER(dbl), vp]
+        L.dg_energy_noalloc.argtypes = [vp, vp, vp]
         L.dg_stable_dt.argtypes = [vp, dbl, ctypes.POINTER(dbl)]
         L.dg_setup_query_batch.argtypes = [ctypes.POINTER(_Mesh), i32, ctypes.POINTER(_Opts),
                                            ctypes.POINTER(ctypes.c_size_t)]
@@ -276,6 +277,15 @@ class Solver:
         e = ctypes.c_double()
         _check(lib().dg_energy(self._h, ctypes.byref(e), _stream_ptr(stream)))
         return e.value
+
+    def energy_noalloc(self, out, stream=None):
+        """dg_energy_noalloc: the energy into out[0] (a float64 CUDA tensor) on the stream,
+        without allocating or synchronising."""
+        import torch
+        if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 1 and out.is_contiguous()):
+            raise DGError(-1, "expected a contiguous float64 CUDA tensor with at least one element")
+        _check(lib().dg_energy_noalloc(self._h, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
 
     def _check_tensor(self, t):
         import torch

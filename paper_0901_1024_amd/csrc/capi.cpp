@@ -406,6 +406,8 @@ int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());
     if (rc) return rc;
+    // device address of the allocation-free call's scratch array, once per device
+    HIP_TRY(dgk::noalloc_scratch_init(h->device));
     if (dev_workspace) {
       if (workspace_bytes < h->lay.total) return fail(DG_E_OOM, "workspace smaller than dg_setup_query");
       if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0)
@@ -603,6 +605,26 @@ int dg_energy(const dg_handle* h, double* energy, void* stream) {
   double e = 0.0;
   for (double v : host) e += v;
   *energy = e;
+  return DG_OK;
+}
+
+int dg_energy_noalloc(const dg_handle* h, double* energy_dev, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!energy_dev) return fail(DG_E_ARG, "NULL energy_dev");
+  const int64_t nb = (int64_t(h->K) + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems;
+  if (nb > dgk::kNoallocPartials)
+    return fail(DG_E_ARG, "dg_energy_noalloc: K = " + std::to_string(h->K) + " exceeds the limit of " +
+                              std::to_string(int64_t(dgk::kNoallocPartials) * dgk::kEnergyBlockElems) +
+                              " elements (use dg_energy)");
+  rc = set_device(h);
+  if (rc) return rc;
+  double* part = dgk::noalloc_scratch(h->device);
+  if (!part) return fail(DG_E_STATE, "dg_energy_noalloc: scratch array not set up on this device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo),
+                             h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr, h->K, part, s));
+  HIP_TRY(dgk::launch_sum(part, int(nb), energy_dev, s));
   return DG_OK;
 }
 

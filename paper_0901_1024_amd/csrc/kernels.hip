@@ -14,14 +14,22 @@
 // result on chip, so each field value crosses HBM once per stage.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "host/meshbuild.hpp"
 #include "kernels.hpp"
+
+// Device scratch of the allocation-free energy call: one partial sum per block of elements.
+// Each device holds its own copy for the life of the process; host code must use the address
+// returned by hipGetSymbolAddress on that device (noalloc_scratch), never this name.
+static __device__ __align__(256) double scratch[dgk::kNoallocPartials];
 
 namespace dgk {
 namespace {
 
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;
+constexpr int kMaxDevices = 64;
 
 template <int N>
 struct Dims {
@@ -1204,6 +1212,22 @@ hipError_t launch_energy_t(const void* u, const void* M, const void* geo, const 
   return hipGetLastError();
 }
 
+// Sum of n partial energies by one workgroup: strided per-thread sums, then a tree in LDS
+// (a fixed order, so the result does not depend on timing).
+__global__ __launch_bounds__(kThreads) void sum_kernel(const double* __restrict__ partial, int n,
+                                                       double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < n; q += kThreads) acc += partial[q];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // The VALU kernel reads rows of Np words; an order whose rows are padded is served by the
 // contraction kernel only.
 template <typename T, int N>
@@ -1365,6 +1389,39 @@ hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const vo
                          int K, double* partial, hipStream_t s) {
   return f64 ? dispatch_energy<double>(N, u, M, geo, mat, K, partial, s)
              : dispatch_energy<float>(N, u, M, geo, mat, K, partial, s);
+}
+
+hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s) {
+  sum_kernel<<<1, kThreads, 0, s>>>(partial, n, out);
+  return hipGetLastError();
+}
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  double* p = nullptr;
+  e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace dgk

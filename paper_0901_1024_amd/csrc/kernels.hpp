@@ -62,4 +62,16 @@ constexpr int kEnergyBlockElems = 64;
 hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, const void* mat,
                          int K, double* partial, hipStream_t s);
 
+// out[0] = sum of partial[0 .. n-1] (device pointers), by one workgroup in a fixed order.
+hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s);
+
+// The allocation-free energy call keeps its partial sums in a static device array of
+// kNoallocPartials doubles (512 KiB per device, so K <= kNoallocPartials * kEnergyBlockElems).
+constexpr int kNoallocPartials = 65536;
+// Looks up the device address of that array on `device` once (hipGetSymbolAddress with the
+// device current); later calls return at once. Thread-safe.
+hipError_t noalloc_scratch_init(int device);
+// The address found by noalloc_scratch_init on `device`, or NULL before it.
+double* noalloc_scratch(int device);
+
 }  // namespace dgk
