@@ -19,8 +19,16 @@ An absorbing face (the characteristic absorbing condition named for the scatteri
 Sec. 6) takes a zero exterior state, u+ = 0, with the exterior impedance equal to the interior
 one; the upwind flux then lets outgoing characteristics leave and admits nothing.
 
+Scattered-field form (the incident-field formulation of the scattering example of Sec. 6):
+the unknown is the scattered field u_s = u - u_inc, where u_inc is a known incident plane
+wave that solves Maxwell's equations in vacuum. The volume operator and interior fluxes are
+unchanged (the operator is linear and u_inc is continuous); on a scatterer face the total field
+meets the perfectly conducting wall, E_s+ + E_inc = -(E_s- + E_inc) and H_s+ = H_s-, so the
+jump there is [E] = -2 (E_s- + E_inc(x, t)), [H] = 0. The operator then depends on t, and the
+Runge-Kutta stages evaluate it at t + c_i dt.
+
 Time stepping: the five-stage fourth-order 2N-storage Runge-Kutta method of Carpenter and
-Kennedy cited in Sec. 6: res <- a_i res + dt L(u); u <- u + b_i res.
+Kennedy cited in Sec. 6: res <- a_i res + dt L(u, t + c_i dt); u <- u + b_i res.
 """
 from __future__ import annotations
 
@@ -44,6 +52,30 @@ RK4C = np.array([0.0,
                  2526269341429.0 / 6820363962896.0,
                  2006345519317.0 / 3224310063776.0,
                  2802321613138.0 / 2924317926251.0])
+
+
+class PlaneWave:
+    """Incident plane wave in vacuum: E = p f(k.x - t), H = (k x p) f(k.x - t), with unit
+    direction k, polarisation p orthogonal to k and profile
+    f(s) = c0 + c1 s + c2 sin(c3 s + c4). Any such field solves Maxwell's equations in vacuum
+    (unit wave speed and impedance)."""
+
+    def __init__(self, k, p, c):
+        self.k = np.asarray(k, dtype=np.float64)
+        self.p = np.asarray(p, dtype=np.float64)
+        self.c = np.asarray(c, dtype=np.float64)
+        assert self.k.shape == (3,) and self.p.shape == (3,) and self.c.shape == (5,)
+        assert abs(np.linalg.norm(self.k) - 1.0) < 1e-12 and abs(self.k @ self.p) < 1e-12
+
+    def profile(self, s):
+        c0, c1, c2, c3, c4 = self.c
+        return c0 + c1 * s + c2 * np.sin(c3 * s + c4)
+
+    def fields(self, x, y, z, t):
+        """(6, ...) incident field at the points (x, y, z) and time t."""
+        f = self.profile(self.k[0] * x + self.k[1] * y + self.k[2] * z - t)
+        h = np.cross(self.k, self.p)
+        return np.stack([self.p[0] * f, self.p[1] * f, self.p[2] * f, h[0] * f, h[1] * f, h[2] * f])
 
 
 def _cross(a, b):
@@ -74,10 +106,11 @@ def volume_term(mesh: Mesh, u):
     return _curl_term(mesh.ref, mesh.G, u)
 
 
-def _flux_terms(flat, vM, vP, bnd, nrm, alpha, imp, absorb=None):
+def _flux_terms(flat, vM, vP, bnd, nrm, alpha, imp, absorb=None, scatter=None, einc=None):
     """[n.F - (n.F)*] at face nodes given flat fields (6, K*Np), maps vM/vP (k,4,Nfp),
-    wall flags bnd (k,4), normals nrm (k,4,3), impedances imp = (zm, zp, ym, yp) and
-    absorbing-face flags absorb (k,4, a subset of the walls; None = none)."""
+    wall flags bnd (k,4), normals nrm (k,4,3), impedances imp = (zm, zp, ym, yp),
+    absorbing-face flags absorb (k,4, a subset of the walls; None = none), scatterer-face
+    flags scatter (k,4, walls) and the incident E at the face nodes einc (3,k,4,Nfp)."""
     uM = flat[:, vM]
     uP = flat[:, vP]
     b = bnd[:, :, None]
@@ -86,6 +119,10 @@ def _flux_terms(flat, vM, vP, bnd, nrm, alpha, imp, absorb=None):
     if absorb is not None:
         # absorbing face: zero exterior state
         uP = np.where(np.asarray(absorb, dtype=bool)[None, :, :, None], 0.0, uP)
+    if scatter is not None:
+        # scatterer face: the total field meets the wall, E+ = -E- - 2 E_inc, H+ = H-
+        sc = np.asarray(scatter, dtype=bool)[None, :, :, None]
+        uP = np.where(sc, np.concatenate([-uM[:3] - 2.0 * einc, uM[3:]]), uP)
     dE = uP[:3] - uM[:3]
     dH = uP[3:] - uM[3:]
     n = np.moveaxis(nrm, 2, 0)[:, :, :, None]  # 3, k, 4, 1
@@ -117,12 +154,25 @@ def _check_absorb(mesh: Mesh, absorb):
     return absorb
 
 
-def surface_flux(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
+def _incident_at_faces(mesh: Mesh, vM, scatter, incident, t):
+    """Incident E at the face nodes vM (3, k, 4, Nfp) at time t, or None without scatterers."""
+    if scatter is None:
+        return None
+    x = mesh.x.reshape(3, -1)[:, vM]
+    if incident is None:
+        return np.zeros_like(x)
+    return incident.fields(x[0], x[1], x[2], t)[:3]
+
+
+def surface_flux(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None, scatter=None,
+                 incident=None, t=0.0):
     """[n.F - (n.F)*] at every face node, (6, K, 4, Nfp), not yet scaled by Fscale."""
     K, Np = u.shape[1], u.shape[2]
     elems = np.arange(K)
+    scatter = _check_absorb(mesh, scatter)
     return _flux_terms(u.reshape(6, K * Np), mesh.vmapM, mesh.vmapP, mesh.boundary, mesh.n, alpha,
-                       _impedances(mesh, elems, eps, mu), _check_absorb(mesh, absorb))
+                       _impedances(mesh, elems, eps, mu), _check_absorb(mesh, absorb), scatter,
+                       _incident_at_faces(mesh, mesh.vmapM, scatter, incident, t))
 
 
 def _assemble(ref, vol, flux, Fscale, eps_k, mu_k):
@@ -136,21 +186,24 @@ def _assemble(ref, vol, flux, Fscale, eps_k, mu_k):
     return out
 
 
-def rhs(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
+def rhs(mesh: Mesh, u, alpha=1.0, eps=None, mu=None, absorb=None, scatter=None, incident=None, t=0.0):
     """Semi-discrete right-hand side du/dt, u of shape (6, K, Np), FP64. eps, mu: per-element
-    permittivity and permeability (None = 1); absorb: (K, 4) absorbing-face flags."""
+    permittivity and permeability (None = 1); absorb: (K, 4) absorbing-face flags; scatter:
+    (K, 4) scatterer-face flags of the scattered-field form, with the incident PlaneWave
+    `incident` (None = no incident field) at time t."""
     vol = volume_term(mesh, u)
-    flux = surface_flux(mesh, u, alpha, eps, mu, absorb)            # 6, K, 4, Nfp
+    flux = surface_flux(mesh, u, alpha, eps, mu, absorb, scatter, incident, t)   # 6, K, 4, Nfp
     e = None if eps is None else np.asarray(eps, dtype=np.float64)
     m = None if mu is None else np.asarray(mu, dtype=np.float64)
     return _assemble(mesh.ref, vol, flux, mesh.Fscale, e, m)
 
 
-def rhs_at(mesh: Mesh, u, elems, alpha=1.0, eps=None, mu=None, absorb=None):
+def rhs_at(mesh: Mesh, u, elems, alpha=1.0, eps=None, mu=None, absorb=None, scatter=None,
+           incident=None, t=0.0):
     """The same right-hand side evaluated only at the elements `elems`: (6, len, Np). Face
     maps are computed for those elements only, so the mesh may be built with
-    compute_maps=False. eps, mu (per element, None = 1) and absorb ((K, 4) absorbing-face
-    flags) as in rhs()."""
+    compute_maps=False. eps, mu (per element, None = 1), absorb ((K, 4) absorbing-face
+    flags), scatter, incident and t as in rhs()."""
     from .mesh import face_maps
     elems = np.asarray(elems, dtype=np.int64)
     ref = mesh.ref
@@ -158,8 +211,11 @@ def rhs_at(mesh: Mesh, u, elems, alpha=1.0, eps=None, mu=None, absorb=None):
     vol = _curl_term(ref, mesh.G[elems], u[:, elems, :])
     vM, vP = face_maps(mesh.x, mesh.EToE, mesh.EToF, ref.Fmask, elems)
     absorb = _check_absorb(mesh, absorb)
+    scatter = _check_absorb(mesh, scatter)
+    sc = None if scatter is None else scatter[elems]
     flux = _flux_terms(u.reshape(6, K * Np), vM, vP, mesh.boundary[elems], mesh.n[elems], alpha,
-                       _impedances(mesh, elems, eps, mu), None if absorb is None else absorb[elems])
+                       _impedances(mesh, elems, eps, mu), None if absorb is None else absorb[elems],
+                       sc, _incident_at_faces(mesh, vM, sc, incident, t))
     e = None if eps is None else np.asarray(eps, dtype=np.float64)[elems]
     m = None if mu is None else np.asarray(mu, dtype=np.float64)[elems]
     return _assemble(ref, vol, flux, mesh.Fscale[elems], e, m)
@@ -178,12 +234,13 @@ def rhs_range(mesh: Mesh, u, k0, k1, alpha=1.0):
     return _assemble(ref, vol, flux, mesh.Fscale[sl], None, None)
 
 
-def lsrk4_step(mesh: Mesh, u, dt, res=None, **kw):
-    """One five-stage low-storage RK4 step; returns (u_new, res_new)."""
+def lsrk4_step(mesh: Mesh, u, dt, res=None, t=0.0, **kw):
+    """One five-stage low-storage RK4 step from time t; returns (u_new, res_new). Stage i
+    evaluates the right-hand side at t + c_i dt (only the scattered-field form depends on t)."""
     u = np.array(u, dtype=np.float64, copy=True)
     res = np.zeros_like(u) if res is None else np.array(res, dtype=np.float64, copy=True)
-    for a, b in zip(RK4A, RK4B):
-        res = a * res + dt * rhs(mesh, u, **kw)
+    for a, b, c in zip(RK4A, RK4B, RK4C):
+        res = a * res + dt * rhs(mesh, u, t=t + c * dt, **kw)
         u = u + b * res
     return u, res
 
@@ -197,7 +254,7 @@ def face_rings(mesh: Mesh, elems, depth):
     return rings
 
 
-def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0, **kw):
+def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0, t=0.0, **kw):
     """One LSRK4 step from res = 0, evaluated only where it is needed for `elems`.
 
     A stage's right-hand side at an element reads only that element and its face neighbours,
@@ -208,9 +265,9 @@ def lsrk4_step_at(mesh: Mesh, u, dt, elems, alpha=1.0, **kw):
     rings = face_rings(mesh, elems, 5)
     u = np.array(u, dtype=np.float64, copy=True)
     res = np.zeros_like(u)
-    for i, (a, b) in enumerate(zip(RK4A, RK4B)):
+    for i, (a, b, c) in enumerate(zip(RK4A, RK4B, RK4C)):
         S = rings[4 - i]
-        r = rhs_at(mesh, u, S, alpha, **kw)
+        r = rhs_at(mesh, u, S, alpha, t=t + c * dt, **kw)
         res[:, S] = a * res[:, S] + dt * r
         u[:, S] = u[:, S] + b * res[:, S]
     return u[:, np.asarray(elems, dtype=np.int64)]

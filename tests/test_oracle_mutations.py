@@ -43,26 +43,26 @@ ORIG_VOLUME = W.volume_term
 ORIG_FLUX = W.surface_flux
 
 
-def _flux_wrong_normal(mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
+def _flux_wrong_normal(mesh, u, *args, **kw):
     saved = mesh.n
     mesh.n = -saved
     try:
-        return ORIG_FLUX(mesh, u, alpha, eps, mu, absorb)
+        return ORIG_FLUX(mesh, u, *args, **kw)
     finally:
         mesh.n = saved
 
 
-def _flux_no_neighbour(mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
+def _flux_no_neighbour(mesh, u, *args, **kw):
     saved = mesh.vmapP
     mesh.vmapP = mesh.vmapM
     try:
-        return ORIG_FLUX(mesh, u, alpha, eps, mu, absorb)
+        return ORIG_FLUX(mesh, u, *args, **kw)
     finally:
         mesh.vmapP = saved
 
 
-def _flux_half(mesh, u, alpha=1.0, eps=None, mu=None, absorb=None):
-    return 0.5 * ORIG_FLUX(mesh, u, alpha, eps, mu, absorb)
+def _flux_half(mesh, u, *args, **kw):
+    return 0.5 * ORIG_FLUX(mesh, u, *args, **kw)
 
 
 @pytest.mark.parametrize("name,target,replacement", [
