@@ -490,8 +490,8 @@ def main():
                 "frac": round(tflops_k / PEAKS_TFLOPS[prec], 4)}
     roof["traffic"] = None if args.material else recorded_traffic(N, prec, K)
     mat = "true" if args.material else "false"
-    roof["kernel"] = (f"mfma_stage_kernel<{N},true,{mat}>" if prec == "f32" and N in (3, 4)
-                      else f"hmfma_stage_kernel<{N},true,{mat}>" if prec == "f32" and N in (5, 6)
+    roof["kernel"] = (f"mfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (3, 4)
+                      else f"hmfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (5, 6, 7)
                       else f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>")
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)

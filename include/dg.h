@@ -58,7 +58,8 @@ typedef struct {
   const int8_t* face_bc;  /* K x 4 or NULL, face f of element k being the triple F(f+1) of
                              etov[k] as given (before the orientation fix): 0 = automatic
                              (an unmatched face is a perfectly conducting wall), 1 = wall,
-                             2 = absorbing; nonzero on a matched face is DG_E_MESH */
+                             2 = absorbing, 3 = scatterer (scattered-field form, see
+                             dg_set_incident); nonzero on a matched face is DG_E_MESH */
   const double* eps;      /* K permittivities (> 0, finite) or NULL (= 1 everywhere) */
   const double* mu;       /* K permeabilities (> 0, finite) or NULL (= 1 everywhere);
                              a bad value is DG_E_ARG */
@@ -140,6 +141,28 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream);
  * field component separately; eps = mu = 1 in vacuum), accumulated in double.
  * Synchronises `stream`. */
 int dg_energy(const dg_handle* h, double* energy, void* stream);
+
+/* ---- Scattered-field form (the incident-field formulation of the scattering example of
+ * Sec. 6). The state is the scattered field; the total field is it plus a known incident plane
+ * wave in vacuum, E_inc = p f(k.x - t), H_inc = (k x p) f(k.x - t), with profile
+ * f(s) = c0 + c1 s + c2 sin(c3 s + c4). On scatterer faces (face_bc = 3) the total field meets
+ * a perfectly conducting wall: E+ = -E- - 2 E_inc(x, t), H+ = H-. The operator then depends on
+ * time: the handle keeps the time of its next step (initially 0; each RK step advances it by
+ * dt, also inside dg_solve's graph), dg_rhs evaluates at that time and the RK stages at
+ * t + c_i dt. Not available in a batch handle (DG_E_UNSUPPORTED at setup). */
+
+/* Incident wave: direction k (3, normalised by the call), polarisation p (3, orthogonal to k;
+ * its length is the amplitude) and profile (c0..c4). Computes k.x at every scatterer face node
+ * in FP64 on the host and uploads it with the record; synchronises `stream`. Without this call
+ * the incident field is zero and scatterer faces act as walls. DG_E_ARG if the mesh has no
+ * scatterer faces or the arguments are not finite or p is not orthogonal to k. */
+int dg_set_incident(dg_handle* h, const double* k, const double* p, const double* profile, void* stream);
+
+/* Set the time of the handle's next step (any handle; it matters only with scatterer faces). */
+int dg_set_time(dg_handle* h, double t, void* stream);
+
+/* The time of the handle's next step (host-side copy; does not synchronise). */
+int dg_get_time(const dg_handle* h, double* t);
 
 /* The energy of dg_energy, computed without allocating anything and without synchronising:
  * for callers that cannot allocate device memory (code under HIP graph capture, tight serving

@@ -25,7 +25,8 @@ _ERRS = {-1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_UNSUPPORTED", -4: "DG_E_OOM"
 EXPORTS = ["dg_setup_query", "dg_setup", "dg_free", "dg_last_error", "dg_info", "dg_nodes",
            "dg_get_maps", "dg_get_operators", "dg_set_fields", "dg_get_fields", "dg_rhs",
            "dg_rk_step", "dg_solve", "dg_energy", "dg_energy_noalloc", "dg_stable_dt", "dg_setup_query_batch",
-           "dg_setup_batch", "dg_batch_info", "dg_batch_stable_dt", "dg_set_batch_dt"]
+           "dg_setup_batch", "dg_batch_info", "dg_batch_stable_dt", "dg_set_batch_dt", "dg_set_incident",
+           "dg_set_time", "dg_get_time"]
 
 
 class DGError(RuntimeError):
@@ -91,6 +92,9 @@ def lib():
         L.dg_batch_info.argtypes = [vp, ctypes.POINTER(i32), vp]
         L.dg_batch_stable_dt.argtypes = [vp, dbl, vp]
         L.dg_set_batch_dt.argtypes = [vp, vp, vp]
+        L.dg_set_incident.argtypes = [vp, vp, vp, vp, vp]
+        L.dg_set_time.argtypes = [vp, dbl, vp]
+        L.dg_get_time.argtypes = [vp, ctypes.POINTER(dbl)]
         for name in EXPORTS:
             if name != "dg_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -141,8 +145,8 @@ def _opts_struct(order, precision, reorder, device):
     return o
 
 
-def setup_query(vxyz, etov, order, precision="f64", reorder=1, eps=None, mu=None):
-    m, _keep = _mesh_struct(vxyz, etov, eps=eps, mu=mu)
+def setup_query(vxyz, etov, order, precision="f64", reorder=1, eps=None, mu=None, face_bc=None):
+    m, _keep = _mesh_struct(vxyz, etov, face_bc=face_bc, eps=eps, mu=mu)
     o = _opts_struct(order, precision, reorder, 0)
     n = ctypes.c_size_t()
     _check(lib().dg_setup_query(ctypes.byref(m), ctypes.byref(o), ctypes.byref(n)))
@@ -277,6 +281,26 @@ class Solver:
         e = ctypes.c_double()
         _check(lib().dg_energy(self._h, ctypes.byref(e), _stream_ptr(stream)))
         return e.value
+
+    def set_incident(self, k, p, profile, stream=None):
+        """Incident plane wave of the scattered-field form (dg_set_incident): direction k,
+        polarisation p, profile f(s) = c0 + c1 s + c2 sin(c3 s + c4)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        c = np.ascontiguousarray(profile, dtype=np.float64)
+        if k.shape != (3,) or p.shape != (3,) or c.shape != (5,):
+            raise DGError(-1, "k, p need 3 values and the profile 5")
+        _check(lib().dg_set_incident(self._h, k.ctypes.data_as(ctypes.c_void_p), p.ctypes.data_as(ctypes.c_void_p),
+                                     c.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+
+    def set_time(self, t, stream=None):
+        _check(lib().dg_set_time(self._h, float(t), _stream_ptr(stream)))
+
+    @property
+    def time(self):
+        t = ctypes.c_double()
+        _check(lib().dg_get_time(self._h, ctypes.byref(t)))
+        return t.value
 
     def energy_noalloc(self, out, stream=None):
         """dg_energy_noalloc: the energy into out[0] (a float64 CUDA tensor) on the stream,

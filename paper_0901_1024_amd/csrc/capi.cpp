@@ -31,13 +31,17 @@ constexpr double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -24042679903
 constexpr double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                             1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                             2277821191437.0 / 14882151754819.0};
+// stage times: stage i evaluates the operator at t + c_i dt
+constexpr double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                            2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
 struct Layout {
   size_t state = 0;   // bytes of one canonical [6][K][Np] array
   size_t istate = 0;  // bytes of one internal [K][6][S] array (S = dgk::row_stride)
   size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
-      off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, off_geo_dt, off_mat_dt, total;
-  size_t opcat_bytes = 0, mat_bytes = 0, geo_dt_bytes = 0, mat_dt_bytes = 0;
+      off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, off_geo_dt, off_mat_dt, off_src,
+      off_phase, total;
+  size_t opcat_bytes = 0, mat_bytes = 0, geo_dt_bytes = 0, mat_dt_bytes = 0, src_bytes = 0, phase_bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -47,7 +51,10 @@ int opfrag_words_for(int N, size_t ts) { return (ts == 4 && dgk::mfma_order(N)) 
 
 // batch: a second copy of the geometric (and material) records scaled by each mesh's time
 // step, read by the RK stages (the right-hand side is linear in them).
-Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool batch = false) {
+// nscat: scatterer faces (scattered-field form): an incident record and Nfp phases per face,
+// always in double.
+Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool batch = false,
+                   int64_t nscat = 0) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -77,8 +84,20 @@ Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool
   L.off_geo_dt = take(L.geo_dt_bytes);
   L.mat_dt_bytes = batch ? L.mat_bytes : 0;
   L.off_mat_dt = take(L.mat_dt_bytes);
+  L.src_bytes = nscat ? size_t(dgk::kSrcRecWords) * sizeof(double) : 0;
+  L.off_src = take(L.src_bytes);
+  L.phase_bytes = size_t(nscat) * Nfp * sizeof(double);
+  L.off_phase = take(L.phase_bytes);
   L.total = o;
   return L;
+}
+
+// Scatterer faces requested by face_bc (value 3).
+int64_t count_scatterers(const dg_mesh* mesh) {
+  int64_t n = 0;
+  if (mesh && mesh->face_bc)
+    for (int64_t q = 0; q < int64_t(mesh->K) * 4; ++q) n += mesh->face_bc[q] == 3;
+  return n;
 }
 
 int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
@@ -115,6 +134,10 @@ struct dg_handle {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraph_t graph[2] = {nullptr, nullptr};
   double graph_dt[2] = {0.0, 0.0};
+  // scattered-field form: number of scatterer faces and the time at the start of the next
+  // step (the device keeps the same value in the incident record; both add dt per step)
+  int64_t nscat = 0;
+  double t = 0.0;
 
   bool f64() const { return prec == DG_F64; }
   void* at(size_t off) const { return ws + off; }
@@ -222,6 +245,10 @@ int upload(dg_handle* h, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_nbr), nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_elem_of), M.elem_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_pos_of), M.pos_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
+  if (h->nscat) {   // no incident wave until dg_set_incident: scatterer faces act as walls
+    HIP_TRY(hipMemsetAsync(h->at(h->lay.off_src), 0, h->lay.src_bytes, s));
+    HIP_TRY(hipMemsetAsync(h->at(h->lay.off_phase), 0, h->lay.phase_bytes, s));
+  }
   HIP_TRY(hipMemsetAsync(h->u(0), 0, h->lay.istate, s));
   HIP_TRY(hipMemsetAsync(h->u(1), 0, h->lay.istate, s));
   HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.istate, s));
@@ -241,7 +268,7 @@ int set_device(const dg_handle* h) {
 }
 
 int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, double b, double dt,
-                 hipStream_t s) {
+                 hipStream_t s, double toff = 0.0) {
   dgk::StageArgs args;
   args.u_in = in;
   args.out = out;
@@ -254,16 +281,24 @@ int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, 
   args.a = a;
   args.b = b;
   args.dt = dt;
+  if (h->nscat) {
+    args.src.rec = static_cast<const double*>(h->at(h->lay.off_src));
+    args.src.phase = static_cast<const double*>(h->at(h->lay.off_phase));
+    args.src.toff = toff;
+  }
   HIP_TRY(dgk::launch_stage(h->N, h->f64(), stage, h->ops(), args, s));
   return DG_OK;
 }
 
+// One RK step's launches: five stages at t + c_i dt, then (scattered-field form) the device
+// clock advances by dt. The caller advances the host mirror h->t.
 int rk_step_launch(dg_handle* h, double dt, hipStream_t s) {
   for (int i = 0; i < 5; ++i) {
-    int rc = stage_launch(h, true, h->u(h->cur), h->u(1 - h->cur), kRkA[i], kRkB[i], dt, s);
+    int rc = stage_launch(h, true, h->u(h->cur), h->u(1 - h->cur), kRkA[i], kRkB[i], dt, s, kRkC[i] * dt);
     if (rc) return rc;
     h->cur ^= 1;
   }
+  if (h->nscat) HIP_TRY(dgk::launch_advance_clock(static_cast<double*>(h->at(h->lay.off_src)), dt, s));
   return DG_OK;
 }
 
@@ -345,8 +380,8 @@ int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_b
   if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
   const int N = opts->order;
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
-  *workspace_bytes =
-      make_layout(mesh->K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4, mesh->eps || mesh->mu).total;
+  *workspace_bytes = make_layout(mesh->K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4, mesh->eps || mesh->mu,
+                                 false, count_scatterers(mesh)).total;
   return DG_OK;
 }
 
@@ -401,7 +436,9 @@ int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32
   h->ts = h->f64() ? 8 : 4;
   h->S = dgk::row_stride(h->N, h->f64());
   h->device = opts->device;
-  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty(), h->batch);
+  h->nscat = int64_t(h->mesh.scat_face.size());
+  if (h->nscat && h->batch) return fail(DG_E_UNSUPPORTED, "scatterer faces are not supported in a batch");
+  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty(), h->batch, h->nscat);
   if (h->device >= 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());
@@ -550,7 +587,9 @@ int dg_rk_step(dg_handle* h, double dt, void* stream) {
   if (!std::isfinite(dt)) return fail(DG_E_ARG, "dt must be finite");
   rc = set_device(h);
   if (rc) return rc;
-  return rk_step_launch(h, dt, static_cast<hipStream_t>(stream));
+  rc = rk_step_launch(h, dt, static_cast<hipStream_t>(stream));
+  if (!rc) h->t += dt;
+  return rc;
 }
 
 int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
@@ -582,9 +621,17 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
       HIP_TRY(hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0));
       h->graph_dt[p] = dt;
     }
-    for (int64_t i = 0; i + 1 < nsteps; i += 2) HIP_TRY(hipGraphLaunch(h->gexec[p], s));
+    for (int64_t i = 0; i + 1 < nsteps; i += 2) {
+      HIP_TRY(hipGraphLaunch(h->gexec[p], s));
+      h->t += dt;
+      h->t += dt;
+    }
   }
-  if (nsteps % 2) return rk_step_launch(h, dt, s);
+  if (nsteps % 2) {
+    rc = rk_step_launch(h, dt, s);
+    if (!rc) h->t += dt;
+    return rc;
+  }
   return DG_OK;
 }
 
@@ -625,6 +672,62 @@ int dg_energy_noalloc(const dg_handle* h, double* energy_dev, void* stream) {
   HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo),
                              h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr, h->K, part, s));
   HIP_TRY(dgk::launch_sum(part, int(nb), energy_dev, s));
+  return DG_OK;
+}
+
+int dg_set_incident(dg_handle* h, const double* k, const double* p, const double* profile, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!h->nscat) return fail(DG_E_ARG, "the mesh has no scatterer faces (face_bc = 3)");
+  if (!k || !p || !profile) return fail(DG_E_ARG, "NULL argument");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(k[i]) || !std::isfinite(p[i])) return fail(DG_E_ARG, "k and p must be finite");
+  for (int i = 0; i < 5; ++i)
+    if (!std::isfinite(profile[i])) return fail(DG_E_ARG, "profile coefficients must be finite");
+  const double kn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  if (!(kn > 0.0)) return fail(DG_E_ARG, "k must not be zero");
+  const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
+  const double pn = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  if (std::fabs(kh[0] * p[0] + kh[1] * p[1] + kh[2] * p[2]) > 1e-9 * std::max(pn, 1e-300))
+    return fail(DG_E_ARG, "the polarisation p must be orthogonal to k");
+  rc = set_device(h);
+  if (rc) return rc;
+  // phase k.x at the face nodes of each scatterer face, from the FP64 node coordinates
+  const int Np = h->Np, Nfp = h->Nfp, K = h->K;
+  std::vector<double> ph(size_t(h->nscat) * Nfp);
+  for (int64_t i = 0; i < h->nscat; ++i) {
+    const int32_t sf = h->mesh.scat_face[size_t(i)];
+    const int ue = h->mesh.elem_of[sf / 4], f = sf % 4;
+    for (int j = 0; j < Nfp; ++j) {
+      const size_t n = size_t(ue) * Np + h->ref.Fmask[size_t(f) * Nfp + j];
+      const size_t KN = size_t(K) * Np;
+      ph[size_t(i) * Nfp + j] = kh[0] * h->mesh.x[n] + kh[1] * h->mesh.x[KN + n] + kh[2] * h->mesh.x[2 * KN + n];
+    }
+  }
+  const double rec[dgk::kSrcRecWords] = {p[0], p[1], p[2], profile[0], profile[1], profile[2], profile[3],
+                                         profile[4], h->t};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_phase), ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_src), rec, sizeof(rec), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // host staging buffers die at return
+  return DG_OK;
+}
+
+int dg_set_time(dg_handle* h, double t, void* stream) {
+  int rc = need_device(h);
+  if (rc) return rc;
+  if (!std::isfinite(t)) return fail(DG_E_ARG, "t must be finite");
+  rc = set_device(h);
+  if (rc) return rc;
+  if (h->nscat)
+    HIP_TRY(dgk::launch_set_clock(static_cast<double*>(h->at(h->lay.off_src)), t, static_cast<hipStream_t>(stream)));
+  h->t = t;
+  return DG_OK;
+}
+
+int dg_get_time(const dg_handle* h, double* t) {
+  if (!h || !t) return fail(DG_E_ARG, "NULL argument");
+  *t = h->t;
   return DG_OK;
 }
 

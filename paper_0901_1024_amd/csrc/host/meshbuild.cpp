@@ -85,7 +85,7 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
     }
     q = e;
   }
-  m.absorbing.assign(size_t(K) * 4, 0);
+  m.wall_kind.assign(size_t(K) * 4, 0);
   if (face_bc) {
     for (int k = 0; k < K; ++k)
       for (int fu = 0; fu < 4; ++fu) {
@@ -93,9 +93,9 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
         const int f = swapped[k] && fu < 2 ? 1 - fu : fu;   // the user's face in internal numbering
         const size_t q = size_t(k) * 4 + f;
         const bool boundary = m.etoe[q] == k && m.etof[q] == f;
-        if (bc < 0 || bc > 2) throw std::runtime_error("unsupported face condition");
+        if (bc < 0 || bc > 3) throw std::runtime_error("unsupported face condition");
         if (bc != 0 && !boundary) throw std::runtime_error("boundary condition on an interior face");
-        m.absorbing[q] = bc == 2;
+        m.wall_kind[q] = bc;
       }
   }
 
@@ -217,9 +217,16 @@ MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, cons
     int k = m.elem_of[i];
     for (int f = 0; f < 4; ++f) {
       size_t q = size_t(k) * 4 + f;
-      m.face_code[size_t(i) * 4 + f] =
-          (m.orient[q] >= 0) ? pack_face(m.pos_of[m.etoe[q]], m.orient[q], m.etof[q])
-                             : (m.absorbing[q] ? kFaceAbsorbing : kFacePec);
+      int32_t code = kFacePec;
+      if (m.orient[q] >= 0) {
+        code = pack_face(m.pos_of[m.etoe[q]], m.orient[q], m.etof[q]);
+      } else if (m.wall_kind[q] == 2) {
+        code = kFaceAbsorbing;
+      } else if (m.wall_kind[q] == 3) {
+        code = kFaceScatter0 - int32_t(m.scat_face.size());
+        m.scat_face.push_back(i * 4 + f);
+      }
+      m.face_code[size_t(i) * 4 + f] = code;
     }
   }
   return m;

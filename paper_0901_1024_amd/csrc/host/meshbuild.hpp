@@ -25,10 +25,12 @@ constexpr int kGeoNormal = 9;
 constexpr int kGeoJ = 25;
 
 // Packed face record: kFacePec for a perfectly conducting wall, kFaceAbsorbing for an
-// absorbing face (zero exterior state), else
+// absorbing face (zero exterior state), kFaceScatter0 - i for scatterer face i (a wall for the
+// total field of the scattered-field form: E+ = -E- - 2 E_inc, H+ = H-), else
 // (neighbour internal id << 5) | (orientation code << 2) | neighbour face.
 constexpr int32_t kFacePec = -1;
 constexpr int32_t kFaceAbsorbing = -2;
+constexpr int32_t kFaceScatter0 = -3;
 inline int32_t pack_face(int32_t nbr, int orient, int nface) {
   return (nbr << 5) | (orient << 2) | nface;
 }
@@ -50,7 +52,11 @@ struct MeshData {
   std::vector<int32_t> etov;         // K x 4 after the orientation fix (user order)
   std::vector<int32_t> etoe, etof;   // K x 4 (user order); boundary faces point to themselves
   std::vector<int32_t> orient;       // K x 4 orientation code of interior faces, -1 on walls
-  std::vector<int8_t> absorbing;     // K x 4 (user order, internal face numbering)
+  std::vector<int8_t> wall_kind;     // K x 4 (user order, internal face numbering): face_bc
+                                     // of a boundary face (0 automatic, 1 wall, 2 absorbing,
+                                     // 3 scatterer), 0 on interior faces
+  std::vector<int32_t> scat_face;    // scatterer faces in face-record order: internal
+                                     // element * 4 + face
   std::vector<double> geo;           // K x kGeoStride (user order)
   std::vector<double> x;             // 3 x K x Np physical node coordinates (user order)
   std::vector<int32_t> elem_of;      // internal position -> user element
@@ -60,7 +66,8 @@ struct MeshData {
 
 // Throws std::runtime_error with a message on an invalid mesh (degenerate element, a face
 // shared by more than two elements, bad vertex id). face_bc (K x 4 or null) is indexed by the
-// faces of etov as given: 0 automatic (wall if unmatched), 1 wall, 2 absorbing. group (K or
+// faces of etov as given: 0 automatic (wall if unmatched), 1 wall, 2 absorbing, 3 scatterer
+// (a wall for the total field of the scattered-field form). group (K or
 // null): elements of one group stay contiguous, in group order, under the locality order.
 MeshData build_mesh(const RefOps& R, int nverts, const double* vxyz, int K, const int32_t* etov,
                     const int8_t* face_bc, int reorder, const int32_t* group = nullptr);

@@ -14,6 +14,7 @@
 // result on chip, so each field value crosses HBM once per stage.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "host/meshbuild.hpp"
@@ -42,7 +43,7 @@ struct Dims {
 // Words per (element, field) row of the internal field arrays [K][6][S]: Np, padded to a
 // multiple of 4 (pad words zero) for the orders that the FP32 contraction kernels serve, so
 // that their tiles move in aligned 16-byte chunks.
-constexpr bool contraction_order(int N) { return N >= 3 && N <= 6; }
+constexpr bool contraction_order(int N) { return N >= 3 && N <= 7; }
 template <typename T, int N>
 constexpr int kRowStride = (sizeof(T) == 4 && contraction_order(N)) ? (Dims<N>::Np + 3) / 4 * 4 : Dims<N>::Np;
 
@@ -51,12 +52,28 @@ constexpr int kRowStride = (sizeof(T) == 4 && contraction_order(N)) ? (Dims<N>::
 // takes the neighbour's trace p (six fields).
 template <typename T>
 __device__ __forceinline__ void face_jump(int code, const T (&m)[6], const T (&p)[6], T (&d)[6]) {
-  const bool inner = code >= 0, pec = code == dgh::kFacePec;
+  // a scatterer face is a wall for the total field: m carries E- + E_inc there
+  const bool inner = code >= 0, pec = code == dgh::kFacePec || code <= dgh::kFaceScatter0;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {   // selects, no branches
     const T wall = pec ? (c < 3 ? T(-2) * m[c] : T(0)) : -m[c];
     d[c] = inner ? p[c] - m[c] : wall;
   }
+}
+
+// Scattered-field form: add the incident plane wave E_inc = p f(k.x - t) to the interior E at
+// face node j of scatterer face `code` (<= kFaceScatter0), so that face_jump mirrors the total
+// field. f(s) = c0 + c1 s + c2 sin(c3 s + c4), t = step start + stage offset; evaluated in
+// double for either working precision.
+template <typename T>
+__device__ __forceinline__ void add_incident(const SrcArgs& src, int code, int j, int nfp, T (&m)[6]) {
+  const double* r = src.rec;
+  const double ph = src.phase[size_t(dgh::kFaceScatter0 - code) * nfp + j];
+  const double x = ph - (r[8] + src.toff);
+  const double f = r[3] + r[4] * x + r[5] * sin(r[6] * x + r[7]);
+  m[0] += T(r[0] * f);
+  m[1] += T(r[1] * f);
+  m[2] += T(r[2] * f);
 }
 
 // Upwind flux of Sec. 6 at a face node with unit normal n and jump d = (dE, dH), written to
@@ -99,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
     const T* __restrict__ geo, const int32_t* __restrict__ fcode, const T* __restrict__ mat,
     const T* __restrict__ Dr, const T* __restrict__ Ds, const T* __restrict__ Dt,
     const T* __restrict__ LIFT, const int32_t* __restrict__ fmask,
-    const int32_t* __restrict__ nbrnode, int K, int ntiles, T ca, T cb, T cdt) {
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, T ca, T cb, T cdt, SrcArgs inc) {
   using D = Dims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E;
   constexpr int G = dgh::kGeoStride;
@@ -134,6 +151,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(
       const T* up = (le >= 0 && le < nel) ? us + le * 6 * NP + nn : u_in + size_t(nb) * 6 * NP + nn;
       for (int c = 0; c < 6; ++c) p[c] = up[c * NP];
     }
+    if (inc.rec && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
     face_jump(code, m, p, d);
     if (mat) {
       const T* mw = mat + size_t(elem) * dgh::kMatStride + dgh::kMatFace + 4 * f;
@@ -276,12 +294,12 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // MAT: heterogeneous medium. 1/eps and 1/mu of the tile's elements ride in the unused last
 // words of each element row of the padded tile (up_s) and scale the operand coefficients;
 // the face weights of the material records are prefetched with the tile into LDS (wmat).
-template <int N, bool STAGE, bool MAT>
+template <int N, bool STAGE, bool MAT, bool SRC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<N>::WPE, MDims<N>::WPE))) void mfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
     const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
-    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt, SrcArgs inc) {
   using D = MDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
                 NF = D::NF, KS = D::KS, RSL = D::RSL, NT = D::NT,
@@ -479,7 +497,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<
           float m[6], d[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) m[c] = um[c * NPP];
-          face_jump(fc[e * 4 + f], m, nup[r], d);
+          const int code = fc[e * 4 + f];
+          if (SRC && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
+          face_jump(code, m, nup[r], d);
           const float w[4] = {wm[r].x, wm[r].y, wm[r].z, wm[r].w};
           upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
         }
@@ -737,12 +757,12 @@ struct HDims {
   static_assert(ROWS % 16 == 0, "whole row tiles");
 };
 
-template <int N, bool STAGE, bool MAT>
+template <int N, bool STAGE, bool MAT, bool SRC>
 __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void hmfma_stage_kernel(
     const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
     const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
     const float* __restrict__ opf, const int32_t* __restrict__ fmask,
-    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt) {
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt, SrcArgs inc) {
   using D = HDims<N>;
   constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES,
                 NF = D::NF, KS = D::KS, RSL = D::RSL, RT = D::RT, FIT = D::FIT,
@@ -907,7 +927,9 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
           float m[6], d[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) m[c] = um[c * NP];
-          face_jump(fc[e * 4 + f], m, nup[r], d);
+          const int code = fc[e * 4 + f];
+          if (SRC && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
+          face_jump(code, m, nup[r], d);
           const float w[4] = {wm[r].x, wm[r].y, wm[r].z, wm[r].w};
           upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
         }
@@ -1066,59 +1088,88 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 }
 
 // Resident workgroups for the persistent grid: CUs x workgroups per CU, a multiple of the XCD
-// count (queried once per kernel: the template argument is the kernel itself, so every kernel
-// keeps its own count).
+// count (queried once per kernel and device: the template argument is the kernel itself, so
+// every kernel keeps its own count).
 template <auto Kern>
 int persistent_grid(int threads, int ntiles) {
-  static int cached = 0;
-  if (!cached) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  // resident workgroups of this kernel, per device (the current one); a benign race only
+  // recomputes the same value
+  static std::atomic<int> cached[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = -1;
+  int res = dev >= 0 ? cached[dev].load(std::memory_order_relaxed) : 0;
+  if (!res) {
+    int cus = 0, per = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, Kern, threads, 0) != hipSuccess || per < 1)
       per = 1, cus = 256;
-    cached = ((cus * per + kXcds - 1) / kXcds) * kXcds;
+    res = ((cus * per + kXcds - 1) / kXcds) * kXcds;
+    if (dev >= 0) cached[dev].store(res, std::memory_order_relaxed);
   }
   const int want = ((ntiles + kXcds - 1) / kXcds) * kXcds;
-  return want < cached ? want : cached;
+  return want < res ? want : res;
 }
 
-template <int N, bool STAGE, bool MAT>
+template <int N, bool STAGE, bool MAT, bool SRC>
 hipError_t launch_mfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = MDims<N>::E;
   const int ntiles = (a.K + E - 1) / E;
-  const int nb = persistent_grid<mfma_stage_kernel<N, STAGE, MAT>>(kThreads, ntiles);
-  mfma_stage_kernel<N, STAGE, MAT><<<nb, kThreads, 0, s>>>(
+  const int nb = persistent_grid<mfma_stage_kernel<N, STAGE, MAT, SRC>>(kThreads, ntiles);
+  mfma_stage_kernel<N, STAGE, MAT, SRC><<<nb, kThreads, 0, s>>>(
       static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
       static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
       static_cast<const float*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
-      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f);
+      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f, a.src);
   return hipGetLastError();
 }
 
-template <int N, bool STAGE, bool MAT>
+template <int N, bool STAGE, bool MAT, bool SRC>
 hipError_t launch_hmfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = HDims<N>::E;
   const int ntiles = (a.K + E - 1) / E;
-  const int nb = persistent_grid<hmfma_stage_kernel<N, STAGE, MAT>>(HDims<N>::THREADS, ntiles);
-  hmfma_stage_kernel<N, STAGE, MAT><<<nb, HDims<N>::THREADS, 0, s>>>(
+  const int nb = persistent_grid<hmfma_stage_kernel<N, STAGE, MAT, SRC>>(HDims<N>::THREADS, ntiles);
+  hmfma_stage_kernel<N, STAGE, MAT, SRC><<<nb, HDims<N>::THREADS, 0, s>>>(
       static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
       static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
       static_cast<const float*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
-      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f);
+      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f, a.src);
   return hipGetLastError();
 }
 
+// The template variant for the stage mode, the medium and the scattered-field form.
+template <int N, template <int, bool, bool, bool> class L>
+hipError_t launch_variant(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const bool mat = a.mat != nullptr, src = a.src.rec != nullptr;
+  if (stage) {
+    if (mat) return src ? L<N, true, true, true>::run(ops, a, s) : L<N, true, true, false>::run(ops, a, s);
+    return src ? L<N, true, false, true>::run(ops, a, s) : L<N, true, false, false>::run(ops, a, s);
+  }
+  if (mat) return src ? L<N, false, true, true>::run(ops, a, s) : L<N, false, true, false>::run(ops, a, s);
+  return src ? L<N, false, false, true>::run(ops, a, s) : L<N, false, false, false>::run(ops, a, s);
+}
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+struct MfmaLaunch {
+  static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
+    return launch_mfma_v<N, STAGE, MAT, SRC>(o, a, s);
+  }
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+struct HmfmaLaunch {
+  static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
+    return launch_hmfma_v<N, STAGE, MAT, SRC>(o, a, s);
+  }
+};
+
 template <int N>
 hipError_t launch_hmfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
-  if (a.mat) return stage ? launch_hmfma_v<N, true, true>(ops, a, s) : launch_hmfma_v<N, false, true>(ops, a, s);
-  return stage ? launch_hmfma_v<N, true, false>(ops, a, s) : launch_hmfma_v<N, false, false>(ops, a, s);
+  return launch_variant<N, HmfmaLaunch>(stage, ops, a, s);
 }
 
 template <int N>
 hipError_t launch_mfma_t(bool stage, const OpsView& ops, const StageArgs& a, hipStream_t s) {
-  if (a.mat) return stage ? launch_mfma_v<N, true, true>(ops, a, s) : launch_mfma_v<N, false, true>(ops, a, s);
-  return stage ? launch_mfma_v<N, true, false>(ops, a, s) : launch_mfma_v<N, false, false>(ops, a, s);
+  return launch_variant<N, MfmaLaunch>(stage, ops, a, s);
 }
 
 template <typename T, int N>
@@ -1137,10 +1188,10 @@ hipError_t launch_stage_t(bool stage, const OpsView& ops, const StageArgs& a, hi
   auto* lf = static_cast<const T*>(ops.LIFT);
   if (stage)
     stage_kernel<T, N, true><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, mt, dr, ds, dt, lf, ops.fmask,
-                                                         ops.nbrnode, a.K, ntiles, T(a.a), T(a.b), T(a.dt));
+                                                         ops.nbrnode, a.K, ntiles, T(a.a), T(a.b), T(a.dt), a.src);
   else
     stage_kernel<T, N, false><<<nblocks, kThreads, 0, s>>>(u, o, r, g, a.fcode, mt, dr, ds, dt, lf, ops.fmask,
-                                                          ops.nbrnode, a.K, ntiles, T(0), T(0), T(0));
+                                                          ops.nbrnode, a.K, ntiles, T(0), T(0), T(0), a.src);
   return hipGetLastError();
 }
 
@@ -1228,6 +1279,11 @@ __global__ __launch_bounds__(kThreads) void sum_kernel(const double* __restrict_
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// The step's start time in the incident record (one thread).
+__global__ void clock_kernel(double* rec, double v, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) rec[8] = add ? rec[8] + v : v;
+}
+
 // The VALU kernel reads rows of Np words; an order whose rows are padded is served by the
 // contraction kernel only.
 template <typename T, int N>
@@ -1278,6 +1334,7 @@ int opcat_words(int N) {
     case 4: return MDims<4>::OPC;
     case 5: return HDims<5>::OPC;
     case 6: return HDims<6>::OPC;
+    case 7: return HDims<7>::OPC;
   }
   return 0;
 }
@@ -1346,6 +1403,7 @@ void opfrag_source(int N, int w, int* n, int* blk, int* col) {
     case 4: return opfrag_source_t<MDims<4>>(w, n, blk, col);
     case 5: return opfrag_source_t<HDims<5>>(w, n, blk, col);
     case 6: return opfrag_source_t<HDims<6>>(w, n, blk, col);
+    case 7: return opfrag_source_t<HDims<7>>(w, n, blk, col);
   }
   *n = *blk = *col = -1;
 }
@@ -1357,6 +1415,7 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
     if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);
     if (N == 5) return launch_hmfma_t<5>(stage, ops, a, s);
     if (N == 6) return launch_hmfma_t<6>(stage, ops, a, s);
+    if (N == 7) return launch_hmfma_t<7>(stage, ops, a, s);
   }
   return f64 ? dispatch_stage<double>(N, stage, ops, a, s) : dispatch_stage<float>(N, stage, ops, a, s);
 }
@@ -1389,6 +1448,16 @@ hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const vo
                          int K, double* partial, hipStream_t s) {
   return f64 ? dispatch_energy<double>(N, u, M, geo, mat, K, partial, s)
              : dispatch_energy<float>(N, u, M, geo, mat, K, partial, s);
+}
+
+hipError_t launch_advance_clock(double* rec, double dt, hipStream_t s) {
+  clock_kernel<<<1, 64, 0, s>>>(rec, dt, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_clock(double* rec, double t, hipStream_t s) {
+  clock_kernel<<<1, 64, 0, s>>>(rec, t, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s) {

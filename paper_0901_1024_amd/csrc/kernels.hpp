@@ -34,6 +34,16 @@ int row_stride(int N, bool f64);
 // operator (n >= Np, col >= Np for a D block, col >= 4 Nfp for LIFT).
 void opfrag_source(int N, int w, int* n, int* blk, int* col);
 
+// Incident field of the scattered-field form (read on scatterer faces only).
+struct SrcArgs {
+  const double* rec = nullptr;    // p (3), profile c0..c4 (5), time at the start of the step (1);
+                                  // NULL when the mesh has no scatterer faces
+  const double* phase = nullptr;  // k.x at the face nodes of scatterer face i: [i][Nfp]
+  double toff = 0.0;              // this stage's time minus the step's start time (c_i dt)
+};
+// Words of the incident record.
+constexpr int kSrcRecWords = 9;
+
 struct StageArgs {
   const void* u_in;  // internal layout [K][6][S], S = row_stride(N, f64)
   void* out;         // rhs (RHS mode) or u_out (stage mode), internal layout
@@ -43,6 +53,7 @@ struct StageArgs {
   const void* mat;   // [K][20] material records of a heterogeneous medium, or NULL (vacuum)
   int K;
   double a, b, dt;   // stage coefficients (stage mode only)
+  SrcArgs src;       // scattered-field form (src.rec == NULL: none)
 };
 
 // One RHS evaluation (stage == false) or one fused LSRK4 stage (stage == true).
@@ -55,6 +66,11 @@ hipError_t launch_to_internal(bool f64, const void* canon, void* internal, const
                               int K, int Np, int S, hipStream_t s);
 hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, const int32_t* pos_of,
                                int K, int Np, int S, hipStream_t s);
+
+// Advance the step's start time in the incident record by dt (after the fifth stage).
+hipError_t launch_advance_clock(double* rec, double dt, hipStream_t s);
+// Set the step's start time in the incident record.
+hipError_t launch_set_clock(double* rec, double t, hipStream_t s);
 
 // Partial energies: one double per block of `energy_block_elems` elements written to
 // `partial`; the caller sums them.

@@ -127,7 +127,7 @@ def test_material_and_face_condition_errors():
     fb = dginputs.faces_on_plane(v, e, 2, 1.0) * 2       # absorbing top faces: accepted
     P.Solver(v, e, 2, device=-1, face_bc=fb, eps=np.full(K, 2.0))
     bad = fb.copy()
-    bad[bad == 2] = 3
+    bad[bad == 2] = 4   # 3 is a scatterer face; 4 is no face condition
     with pytest.raises(P.DGError, match="DG_E_MESH"):
         P.Solver(v, e, 2, device=-1, face_bc=bad)
     interior = np.zeros((K, 4), dtype=np.int8)
@@ -172,3 +172,27 @@ def test_batch_is_the_concatenation_of_its_meshes():
         assert dts[i] == s.stable_dt(0.5)
     with pytest.raises(P.DGError, match="DG_E_ARG"):
         P.BatchSolver([], 2, device=-1)
+
+
+def test_scatterer_faces_on_the_host():
+    """face_bc = 3 marks scatterer faces: accepted on walls, refused on interior faces and in a
+    batch; the incident record and phases enlarge the workspace; the incident wave needs a
+    device handle with scatterer faces."""
+    v, e = dginputs.kuhn_cube(2)
+    K = e.shape[0]
+    sc = dginputs.faces_on_plane(v, e, 2, 0.0) * 3
+    assert sc.any()
+    P.Solver(v, e, 2, device=-1, face_bc=sc)
+    assert P.setup_query(v, e, 3, "f64", face_bc=sc) > P.setup_query(v, e, 3, "f64")
+    m = Mm.Mesh(v, e, R.ref_element(2))
+    k, f = np.argwhere(~m.boundary)[0]
+    interior = np.zeros((K, 4), dtype=np.int8)
+    interior[k, f] = 3
+    with pytest.raises(P.DGError, match="DG_E_MESH"):
+        P.Solver(v, e, 2, device=-1, face_bc=interior)
+    with pytest.raises(P.DGError, match="DG_E_UNSUPPORTED"):
+        P.BatchSolver([{"vxyz": v, "etov": e, "face_bc": sc}, {"vxyz": v, "etov": e}], 2, device=-1)
+    s = P.Solver(v, e, 2, device=-1, face_bc=sc)
+    vec = (ctypes.c_double * 5)(0.0, 0.0, 1.0, 0.0, 0.0)
+    assert P.lib().dg_set_incident(s._h, vec, vec, vec, None) == -6   # DG_E_STATE: host-only
+    assert s.time == 0.0
