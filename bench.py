@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DG RHS GFLOP/s + HBM GB/s (roofline %); solves/s + p50/p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
-PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# Dense peaks of the pipe each precision's contraction runs on. The split-BF16 form takes
+# three bf16 products per FP32 product, so its peak in algorithmic (FP32-equivalent) flops is
+# the bf16 matrix peak over three.
+PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0 / 3}
 
 
 def counts(N):
@@ -194,7 +197,12 @@ def run_batch(args):
         return a.elapsed_time(z) / 1e3
 
     t_plain = timed(lambda n: [s.solve(dts[i], n) for i, s in enumerate(plain)])
-    t_batch = timed(lambda n: [b.solve(1.0, n) for b in batched.values()])
+    t_orders = timed(lambda n: [b.solve(1.0, n) for b in batched.values()])
+    # all orders from one captured graph (a group of the per-order batch handles); the handles
+    # were advanced above, so the plain loop takes the same further steps for the comparison
+    grp = P.Group(list(batched.values()))
+    t_batch = timed(lambda n: grp.solve(np.ones(len(batched)), n))
+    timed(lambda n: [s.solve(dts[i], n) for i, s in enumerate(plain)])
     worst = 0.0
     for N, idx in groups.items():
         got = batched[N].get_fields()
@@ -208,7 +216,7 @@ def run_batch(args):
     Ks = [md["etov"].shape[0] for md in meshes]
     flops = sum(5 * steps * K * flops_per_elem_stage(md["order"]) for K, md in zip(Ks, meshes))
     out = {
-        "metric": "solves/s, batched (one handle per order) vs plain per-mesh loop",
+        "metric": "solves/s, batched (one handle per order, all orders in one graph) vs plain per-mesh loop",
         "value": round(len(meshes) / t_batch, 3), "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": 2, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
         "data": "synthetic",
@@ -219,17 +227,24 @@ def run_batch(args):
         "plain_solves_per_s": round(len(meshes) / t_plain, 3),
         "speedup_batched_over_plain": round(t_plain / t_batch, 3),
         "batched_gflops": round(flops / t_batch / 1e9, 1), "plain_gflops": round(flops / t_plain / 1e9, 1),
-        "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4)},
+        "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4),
+                    "batched_one_graph_per_order": round(t_orders, 4)},
         "max_rel_diff_batched_vs_plain": worst,
     }
-    print(json.dumps(out), flush=True)
+    for s_ in plain:
+        s_.free()
+    grp.free()
+    for b in batched.values():
+        b.free()
+    return out
 
 
-def run_serve(args):
+def run_serve(args, rates=(0.5, 1.0, 2.0)):
     """Serving form: cavity solves with K log-uniform in [2e3, 2e5], N uniform in 3..6, steps
     uniform in [100, 2000], FP32 (seed 5). Capacity = requests / makespan of the plain FIFO loop
     with everything queued at t = 0; then Poisson arrivals at 0.5, 1 and 2 times that rate,
-    served with continuous admission (8 slots, 64 GiB budget) and with the FIFO loop."""
+    served with continuous admission (4 slots: the hardware queues a process gets; 64 GiB budget)
+    and with the FIFO loop."""
     import math
 
     import numpy as np
@@ -268,7 +283,7 @@ def run_serve(args):
     cap = base["solves_per_s"]
     print(f"capacity (FIFO, all queued): {cap:.3f} solves/s", file=sys.stderr, flush=True)
     sweep = []
-    for mult in (0.5, 1.0, 2.0):
+    for mult in rates:
         rate = mult * cap
         a = summary(served().run(requests(rate)))
         b = summary(fifo().run(requests(rate)))
@@ -287,18 +302,22 @@ def run_serve(args):
                                "N uniform in 3..6, steps uniform in [100, 2000], FP32, Poisson arrivals (seed 5)",
                    "slots": args.serve_slots, "chunk_steps": args.serve_chunk, "budget_bytes": budget},
         "capacity_fifo_solves_per_s": cap,
-        "at_2x_rate": {"served_p50_s": top["served"]["p50_latency_s"], "served_p99_s": top["served"]["p99_latency_s"],
-                       "fifo_solves_per_s": top["fifo"]["solves_per_s"], "fifo_p50_s": top["fifo"]["p50_latency_s"],
-                       "fifo_p99_s": top["fifo"]["p99_latency_s"]},
+        f"at_{rates[-1]:g}x_rate": {"served_p50_s": top["served"]["p50_latency_s"],
+                                    "served_p99_s": top["served"]["p99_latency_s"],
+                                    "fifo_solves_per_s": top["fifo"]["solves_per_s"],
+                                    "fifo_p50_s": top["fifo"]["p50_latency_s"],
+                                    "fifo_p99_s": top["fifo"]["p99_latency_s"]},
         "sweep": sweep,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_precision_sweep(args):
-    """Precision form: the (1,1,0) cavity mode on jittered cubes, run to t = T in FP64 and FP32
-    with the same step; per-field relative L2 difference FP32 vs FP64, energy drift
-    E32(t)/E64(t) - 1, and the error of both against the exact mode."""
+    """Precision form: the (1,1,0) cavity mode on jittered cubes, run to t = T in FP64, FP32 and
+    split-BF16 (the last at N = 5, 7) with the same step; per-field relative L2 difference
+    against FP64, energy drift E(t)/E64(t) - 1, and the error of each against the exact mode.
+    N = 7 runs to its own (shorter) time so that the FP64 leg, on the element-wise kernel at
+    that order, stays within a few minutes."""
     import math
 
     import numpy as np
@@ -311,19 +330,19 @@ def run_precision_sweep(args):
     from oracle import refelem as R
 
     results = []
-    for N, n in ((5, args.sweep_n5), (7, args.sweep_n7)):
+    for N, n, T in ((5, args.sweep_n5, args.sweep_t), (7, args.sweep_n7, args.sweep_t7)):
         v, e = dginputs.kuhn_cube(n, jitter=0.15, permute=True)
         m = Mm.Mesh(v, e, R.ref_element(N), compute_maps=False)
         u0 = dginputs.cavity_tm110(*m.x, 0.0)
-        exact = dginputs.cavity_tm110(*m.x, args.sweep_t)
-        row = {"order": N, "K": int(m.K), "t": args.sweep_t}
+        exact = dginputs.cavity_tm110(*m.x, T)
+        row = {"order": N, "K": int(m.K), "t": T}
         fields = {}
-        for prec in ("f64", "f32"):
+        for prec in ("f64", "f32", "bf16x3"):
             s = P.Solver(v, e, N, prec)
             s.set_fields(u0.astype(s.dtype))
             dt0 = s.stable_dt(0.5)
-            nsteps = int(math.ceil(args.sweep_t / dt0))
-            dt = args.sweep_t / nsteps
+            nsteps = int(math.ceil(T / dt0))
+            dt = T / nsteps
             e0 = s.energy()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -343,19 +362,20 @@ def run_precision_sweep(args):
                          "gflops": round(flops / sec / 1e9, 1), "energy_0": e0, "energy_T": s.energy(),
                          "rel_error_vs_exact": err / nrm}
             s.free()
-        d = fields["f32"] - fields["f64"]
         ref = np.linalg.norm(fields["f64"])
-        row["f32_vs_f64_rel_per_field"] = [float(np.linalg.norm(d[f]) / ref) for f in range(6)]
-        row["f32_vs_f64_rel"] = float(np.linalg.norm(d) / ref)
-        row["energy_drift_f32_over_f64"] = row["f32"]["energy_T"] / row["f64"]["energy_T"] - 1.0
+        for prec in ("f32", "bf16x3"):
+            d = fields[prec] - fields["f64"]
+            row[f"{prec}_vs_f64_rel_per_field"] = [float(np.linalg.norm(d[f]) / ref) for f in range(6)]
+            row[f"{prec}_vs_f64_rel"] = float(np.linalg.norm(d) / ref)
+            row[f"energy_drift_{prec}_over_f64"] = row[prec]["energy_T"] / row["f64"]["energy_T"] - 1.0
         results.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
-    out = {"metric": "precision sweep: FP32 vs FP64 error, energy drift, error vs exact mode",
+    out = {"metric": "precision sweep: FP32 and split-BF16 vs FP64 error, energy drift, error vs exact mode",
            "value": results[0]["f32_vs_f64_rel"], "unit": "relative L2", "n_gpus": 1,
            "higher_is_better": False, "data": "synthetic",
-           "config": {"workload": f"(1,1,0) cavity mode to t={args.sweep_t}, jittered permuted cubes, "
-                                  f"N=5 on 6*{args.sweep_n5}^3 and N=7 on 6*{args.sweep_n7}^3 tets, "
-                                  "FP64 and FP32, same step (CFL 0.5)"},
+           "config": {"workload": f"(1,1,0) cavity mode, jittered permuted cubes, N=5 on 6*{args.sweep_n5}^3 "
+                                  f"tets to t={args.sweep_t} and N=7 on 6*{args.sweep_n7}^3 tets to "
+                                  f"t={args.sweep_t7}, FP64, FP32 and split-BF16, same step (CFL 0.5)"},
            "results": results}
     print(json.dumps(out), flush=True)
 
@@ -367,7 +387,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--n", type=int, default=40)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=20)
     ap.add_argument("--reps", type=int, default=20,
@@ -379,11 +399,16 @@ def main():
                     help="precision form: cavity mode in FP64 and FP32 at N = 5 and 7")
     ap.add_argument("--sweep-t", type=float, default=1.0)
     ap.add_argument("--sweep-n5", type=int, default=32)
-    ap.add_argument("--sweep-n7", type=int, default=16)
+    ap.add_argument("--sweep-n7", type=int, default=32)
+    ap.add_argument("--sweep-t7", type=float, default=0.1)
     ap.add_argument("--serve", action="store_true",
                     help="serving form: Poisson arrivals of cavity solves, continuous admission vs FIFO")
     ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--no-solves", action="store_true",
+                    help="skip the compact batched and served legs of the default run")
+    ap.add_argument("--solves-batch-steps", type=int, default=100)
+    ap.add_argument("--solves-serve-requests", type=int, default=12)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-chunk", type=int, default=64)
     ap.add_argument("--material", action="store_true",
                     help="heterogeneous medium (eps, mu log-uniform in [1, 4]) with absorbing z = 1 faces")
@@ -400,10 +425,10 @@ def main():
     import torch
 
     if args.batch:
-        run_batch(args)
+        print(json.dumps(run_batch(args)), flush=True)
         return
     if args.serve:
-        run_serve(args)
+        print(json.dumps(run_serve(args)), flush=True)
         return
     if args.precision_sweep:
         run_precision_sweep(args)
@@ -423,7 +448,7 @@ def main():
 
     N, n, prec = args.order, args.n, args.precision
     Np, Nfp = counts(N)
-    word = 4 if prec == "f32" else 8
+    word = 8 if prec == "f64" else 4
     t_setup = time.perf_counter()
     v, e = dginputs.kuhn_cube(n, jitter=0.15, permute=True)
     kw = {}
@@ -492,6 +517,8 @@ def main():
     mat = "true" if args.material else "false"
     roof["kernel"] = (f"mfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (3, 4)
                       else f"hmfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (5, 6, 7)
+                      else f"dmfma_stage_kernel<{N},true,{mat},false>" if prec == "f64" and N == 3
+                      else f"bmfma_stage_kernel<{N},true,{mat},false>" if prec == "bf16x3"
                       else f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>")
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
@@ -531,6 +558,26 @@ def main():
         cb["speedup_gpu_over_oracle"] = round(gflops / cb["value"], 1)
         cb["speedup_gpu_over_one_core"] = round(gflops / cb["one_core"]["value"], 1)
         out["cpu_baseline"] = cb
+    if not args.no_solves:
+        # the metric's second half, compact: solves/s of the batched form against the plain
+        # per-mesh loop, and solves/s + p50/p99 latency of continuous admission against the
+        # plain FIFO loop at the FIFO capacity rate (smaller runs than --batch / --serve)
+        s.free()
+        args.batch_steps = args.solves_batch_steps
+        bt = run_batch(args)
+        args.serve_requests = args.solves_serve_requests
+        sv = run_serve(args, rates=(1.0,))
+        row = sv["sweep"][0]
+        out["solves"] = {
+            "batched": {"workload": bt["config"]["workload"], "solves_per_s": bt["value"],
+                        "plain_solves_per_s": bt["plain_solves_per_s"],
+                        "speedup_over_plain": bt["speedup_batched_over_plain"]},
+            "served": {"workload": sv["config"]["workload"] + " at the FIFO capacity rate",
+                       "slots": args.serve_slots, "solves_per_s": row["served"]["solves_per_s"],
+                       "p50_s": row["served"]["p50_latency_s"], "p99_s": row["served"]["p99_latency_s"],
+                       "fifo_solves_per_s": row["fifo"]["solves_per_s"], "fifo_p50_s": row["fifo"]["p50_latency_s"],
+                       "fifo_p99_s": row["fifo"]["p99_latency_s"]},
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -39,14 +39,19 @@ extern "C" {
 #define DG_OK 0
 #define DG_E_ARG (-1)         /* invalid argument (NULL pointer, bad size, bad option) */
 #define DG_E_MESH (-2)        /* invalid mesh: degenerate element, face shared by > 2 elements */
-#define DG_E_UNSUPPORTED (-3) /* order outside 1..7, unknown precision */
+#define DG_E_UNSUPPORTED (-3) /* order outside 1..7, unknown precision, DG_BF16X3 outside 5..7 */
 #define DG_E_OOM (-4)         /* device allocation failed or the workspace is too small */
 #define DG_E_HIP (-5)         /* a HIP runtime call failed; message in dg_last_error() */
 #define DG_E_STATE (-6)       /* handle has no device state (built with device = -1) */
+#define DG_E_NUMERIC (-7)     /* dg_solve's numeric monitor found a non-finite or growing energy */
 
 typedef struct dg_handle dg_handle;
 
-typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_precision;
+/* Working precision. DG_BF16X3 (orders 5..7): FP32 state, fluxes and RK update; the volume
+ * and lift contraction splits each operand and operator value x into x_hi + x_lo (bf16 each)
+ * and takes x_hi y_hi + x_hi y_lo + x_lo y_hi on the bf16 matrix cores with FP32 accumulation
+ * (about 3 * 2^-18 relative error per product); field arrays are float. */
+typedef enum { DG_F64 = 0, DG_F32 = 1, DG_BF16X3 = 2 } dg_precision;
 
 /* Mesh description. All arrays are host memory owned by the caller and only read during
  * the call that receives them. */
@@ -71,7 +76,17 @@ typedef struct {
   int32_t reorder;   /* 0 = keep user element order internally, 1 = Morton locality order */
   int32_t device;    /* HIP device ordinal, or -1 for a host-only handle (builder outputs
                         only: dg_info, dg_nodes, dg_get_maps, dg_get_operators) */
-  int32_t reserved[4];
+  int32_t checks;    /* numeric monitor of dg_solve: 0 = off; M > 0 = after every M steps the
+                        energy must be finite and (without scatterer faces) not above its value
+                        at the start of the call by more than 1e-10 (FP64) or 1e-4 (otherwise),
+                        else dg_solve stops with DG_E_NUMERIC; each check synchronises `stream` */
+  int32_t tile_id;   /* stage kernel: 0 = the library's default (the contraction kernel where
+                        the order and precision have one), 1 = element-wise kernel (one thread
+                        per element node; not FP32 N = 4, whose rows are padded, nor DG_BF16X3),
+                        2 = contraction kernel (FP32 N = 3..7, FP64 N = 3, DG_BF16X3);
+                        DG_E_UNSUPPORTED otherwise. An autotuner picks it per order, precision
+                        and mesh size (paper_0901_1024_amd.tune) */
+  int32_t reserved[2];
 } dg_opts;
 
 /* Sizes of a handle. */
@@ -134,7 +149,9 @@ int dg_rhs(dg_handle* h, const void* u_dev, void* rhs_dev, void* stream);
  * state: for each stage i, res = a_i res + dt rhs(u); u = u + b_i res. */
 int dg_rk_step(dg_handle* h, double dt, void* stream);
 
-/* nsteps calls of dg_rk_step, launched from a captured HIP graph of two steps. */
+/* nsteps calls of dg_rk_step, launched from a captured HIP graph of two steps. With
+ * opts.checks = M > 0 the steps run in chunks of M, each followed by the energy check described
+ * at dg_opts (DG_E_NUMERIC: the state holds the steps taken so far, dg_get_time tells when). */
 int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream);
 
 /* Discrete energy 1/2 sum_k J_k (eps_k E_k^T M E_k + mu_k H_k^T M H_k) of the state (each
@@ -208,6 +225,24 @@ int dg_batch_stable_dt(const dg_handle* h, double cfl, double* dt);
 /* Per-mesh time steps (count finite positive values, host array) for the RK stages of a batch
  * handle; the default is 1. Uploads the scaled records and synchronises `stream`. */
 int dg_set_batch_dt(dg_handle* h, const double* dt, void* stream);
+
+/* ---- Group: handles of any orders and precisions advanced together ----------------------
+ * dg_group_solve advances every member handle by nsteps steps of its own dt (dt[i]; for a
+ * batch member, the multiplier of its per-mesh steps) from one captured HIP graph: each
+ * member's two-step sequence is a branch forked from and joined into the calling stream, with
+ * no dependency between branches, so the device may run the members concurrently. Members
+ * keep their own state, face conditions, clocks and ping-pong buffers; a member must not be
+ * used elsewhere while the group solves, and must outlive the group. The numeric monitor of
+ * dg_opts.checks does not run inside a group solve. */
+typedef struct dg_group dg_group;
+
+/* count >= 1 distinct device handles on one device. */
+int dg_group_create(dg_handle* const* members, int32_t count, dg_group** out);
+
+int dg_group_free(dg_group* g);
+
+/* dt: count finite time steps (host array). */
+int dg_group_solve(dg_group* g, const double* dt, int64_t nsteps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -17,16 +17,17 @@ LIB_PATH = os.path.join(PKG, "libdg.so")
 DG_F64 = 0
 DG_F32 = 1
 DG_E_ARG = -1
-_PREC = {"f64": DG_F64, "f32": DG_F32}
+DG_BF16X3 = 2
+_PREC = {"f64": DG_F64, "f32": DG_F32, "bf16x3": DG_BF16X3}
 _ERRS = {-1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_UNSUPPORTED", -4: "DG_E_OOM", -5: "DG_E_HIP",
-         -6: "DG_E_STATE"}
+         -6: "DG_E_STATE", -7: "DG_E_NUMERIC"}
 
 # every symbol declared in include/dg.h
 EXPORTS = ["dg_setup_query", "dg_setup", "dg_free", "dg_last_error", "dg_info", "dg_nodes",
            "dg_get_maps", "dg_get_operators", "dg_set_fields", "dg_get_fields", "dg_rhs",
            "dg_rk_step", "dg_solve", "dg_energy", "dg_energy_noalloc", "dg_stable_dt", "dg_setup_query_batch",
            "dg_setup_batch", "dg_batch_info", "dg_batch_stable_dt", "dg_set_batch_dt", "dg_set_incident",
-           "dg_set_time", "dg_get_time"]
+           "dg_set_time", "dg_get_time", "dg_group_create", "dg_group_free", "dg_group_solve"]
 
 
 class DGError(RuntimeError):
@@ -44,7 +45,8 @@ class _Mesh(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("reorder", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("device", ctypes.c_int32), ("checks", ctypes.c_int32), ("tile_id", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Info(ctypes.Structure):
@@ -95,6 +97,9 @@ def lib():
         L.dg_set_incident.argtypes = [vp, vp, vp, vp, vp]
         L.dg_set_time.argtypes = [vp, dbl, vp]
         L.dg_get_time.argtypes = [vp, ctypes.POINTER(dbl)]
+        L.dg_group_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.dg_group_free.argtypes = [vp]
+        L.dg_group_solve.argtypes = [vp, vp, i64, vp]
         for name in EXPORTS:
             if name != "dg_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -136,13 +141,27 @@ def _mesh_struct(vxyz, etov, face_bc=None, eps=None, mu=None):
     return m, keep
 
 
-def _opts_struct(order, precision, reorder, device):
+def _opts_struct(order, precision, reorder, device, checks=0, tile_id=0):
     o = _Opts()
     o.order = order
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
     o.reorder = reorder
     o.device = device
+    o.checks = checks
+    o.tile_id = tile_id
     return o
+
+
+def _tile_option(tile_id, order, precision, K):
+    """tile_id: None or 0 = the library's default kernel, 1 = element-wise, 2 = contraction,
+    "auto" = the autotuner's choice for this order, precision and mesh size (paper_0901_1024_amd.tune;
+    the default when its table has no entry)."""
+    if tile_id is None:
+        return 0
+    if tile_id == "auto":
+        from . import tune
+        return tune.choose(order, precision, K)
+    return int(tile_id)
 
 
 def setup_query(vxyz, etov, order, precision="f64", reorder=1, eps=None, mu=None, face_bc=None):
@@ -164,13 +183,16 @@ class Solver:
 
     device >= 0: the workspace is a torch uint8 tensor on cuda:device (PyTorch owns the HBM);
     device = -1: host-only handle (builder outputs only).
-    face_bc: (K, 4) int8, 0 automatic, 1 wall, 2 absorbing; eps, mu: (K,) per element.
+    face_bc: (K, 4) int8, 0 automatic, 1 wall, 2 absorbing, 3 scatterer; eps, mu: (K,) per
+    element; checks: numeric monitor interval of solve() in steps (0 = off).
     """
 
     def __init__(self, vxyz, etov, order, precision="f64", reorder=1, device=0, face_bc=None,
-                 stream=None, eps=None, mu=None):
+                 stream=None, eps=None, mu=None, checks=0, tile_id=None):
         L = lib()
         m, keep = _mesh_struct(vxyz, etov, face_bc, eps, mu)
+        self._checks = checks
+        self._tile = _tile_option(tile_id, order, precision, np.asarray(etov).shape[0])
         self._create(order, precision, reorder, device, stream,
                      lambda o, n: L.dg_setup_query(ctypes.byref(m), ctypes.byref(o), n),
                      lambda o, ws, n, s, h: L.dg_setup(ctypes.byref(m), ctypes.byref(o), ws, n, s, h))
@@ -181,7 +203,7 @@ class Solver:
         self.order = order
         self.precision = precision
         self.device = device
-        o = _opts_struct(order, precision, reorder, device)
+        o = _opts_struct(order, precision, reorder, device, getattr(self, "_checks", 0), getattr(self, "_tile", 0))
         h = ctypes.c_void_p()
         self._ws = None
         if device >= 0:
@@ -327,8 +349,9 @@ class BatchSolver(Solver):
     takes n steps of every mesh.
     """
 
-    def __init__(self, meshes, order, precision="f64", reorder=1, device=0, stream=None):
+    def __init__(self, meshes, order, precision="f64", reorder=1, device=0, stream=None, tile_id=None):
         L = lib()
+        self._tile = _tile_option(tile_id, order, precision, sum(np.asarray(md["etov"]).shape[0] for md in meshes))
         arr = (_Mesh * len(meshes))()
         keep = []
         for i, md in enumerate(meshes):
@@ -359,3 +382,82 @@ class BatchSolver(Solver):
 
     def mesh_slice(self, i):
         return slice(int(self.first[i]), int(self.first[i + 1]))
+
+
+class Group:
+    """Handles of any orders and precisions advanced together from one captured graph
+    (dg_group_*): solve(dts, n) takes n steps of every member, member i with step dts[i]."""
+
+    def __init__(self, solvers):
+        L = lib()
+        self.members = list(solvers)
+        arr = (ctypes.c_void_p * len(self.members))(*[s._h.value for s in self.members])
+        g = ctypes.c_void_p()
+        _check(L.dg_group_create(arr, len(self.members), ctypes.byref(g)))
+        self._g = g
+
+    def solve(self, dts, nsteps, stream=None):
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        if d.shape != (len(self.members),):
+            raise DGError(DG_E_ARG, "one time step per member")
+        _check(lib().dg_group_solve(self._g, d.ctypes.data_as(ctypes.c_void_p), int(nsteps), _stream_ptr(stream)))
+
+    def free(self):
+        if getattr(self, "_g", None) is not None and self._g.value:
+            lib().dg_group_free(self._g)
+        self._g = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class MixedBatch:
+    """The batched form over meshes of mixed orders: one batch handle per order (meshes of one
+    order share its launches), all of them advanced by one group graph. Every mesh takes its
+    own stable step (set_dts); fields are per-mesh canonical arrays."""
+
+    def __init__(self, meshes, orders, precision="f32", reorder=1, device=0, stream=None, tile_id=None):
+        self.orders = sorted(set(int(n) for n in orders))
+        self.where = []                     # mesh -> (order index, position in that batch)
+        groups = {n: [] for n in self.orders}
+        for i, (md, n) in enumerate(zip(meshes, orders)):
+            self.where.append((self.orders.index(int(n)), len(groups[int(n)])))
+            groups[int(n)].append(md)
+        self.batches = [BatchSolver(groups[n], n, precision, reorder, device, stream, tile_id) for n in self.orders]
+        self.group = Group(self.batches)
+        self.K = sum(b.K for b in self.batches)
+
+    def stable_dts(self, cfl=0.5):
+        per = [b.stable_dts(cfl) for b in self.batches]
+        return np.array([per[o][j] for o, j in self.where])
+
+    def set_dts(self, dts, stream=None):
+        for o, b in enumerate(self.batches):
+            d = np.empty(b.count)
+            for i, (oo, j) in enumerate(self.where):
+                if oo == o:
+                    d[j] = dts[i]
+            b.set_dts(d, stream)
+
+    def set_fields(self, us, stream=None):
+        for o, b in enumerate(self.batches):
+            parts = [None] * b.count
+            for i, (oo, j) in enumerate(self.where):
+                if oo == o:
+                    parts[j] = np.asarray(us[i], dtype=b.dtype)
+            b.set_fields(np.concatenate(parts, axis=1), stream)
+
+    def get_fields(self, stream=None):
+        outs = [b.get_fields(stream=stream) for b in self.batches]
+        return [outs[o][:, self.batches[o].mesh_slice(j)] for o, j in self.where]
+
+    def solve(self, nsteps, stream=None):
+        self.group.solve(np.ones(len(self.batches)), nsteps, stream)
+
+    def free(self):
+        self.group.free()
+        for b in self.batches:
+            b.free()

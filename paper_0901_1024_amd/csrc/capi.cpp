@@ -46,15 +46,48 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// The fragment-ordered concatenated operator is used by the FP32 contraction kernels only.
-int opfrag_words_for(int N, size_t ts) { return (ts == 4 && dgk::mfma_order(N)) ? dgk::opcat_words(N) : 0; }
+// Bytes of the fragment-ordered concatenated operator of the contraction kernels: FP32, FP64
+// where an FP64 contraction kernel serves the order (same word order in both precisions), or
+// the split-BF16 table (16-bit words).
+bool contraction_kernel(int N, int prec) {
+  return prec == DG_BF16X3 ? dgk::bf16x3_order(N) : prec == DG_F32 ? dgk::mfma_order(N) : dgk::dmfma_order(N);
+}
+
+// tile_id 0 resolved: the contraction kernel where there is one
+int resolve_tile(int N, int prec, int tile_id) {
+  return tile_id ? tile_id : (contraction_kernel(N, prec) ? 2 : 1);
+}
+
+size_t opfrag_bytes_for(int N, int prec, int tile_id = 0) {
+  if (resolve_tile(N, prec, tile_id) != 2) return 0;
+  if (prec == DG_BF16X3) return size_t(dgk::bopcat_words(N)) * 2;
+  const bool used = prec == DG_F32 ? dgk::mfma_order(N) : dgk::dmfma_order(N);
+  return used ? size_t(dgk::opcat_words(N)) * (prec == DG_F64 ? 8 : 4) : 0;
+}
+
+// Nearest bf16 value (round to nearest even) of a double, as a double; its bit pattern is
+// that of the float of the same value, shifted right by 16.
+double round_bf16(double x) {
+  if (x == 0.0 || !std::isfinite(x)) return x;
+  int e = 0;
+  const double f = std::frexp(x, &e);   // x = f 2^e, 0.5 <= |f| < 1: 8 significant bits
+  return std::ldexp(std::nearbyint(std::ldexp(f, 8)), e - 8);
+}
+
+uint16_t bf16_bits(double v) {   // v is a bf16 value
+  const float f = static_cast<float>(v);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return static_cast<uint16_t>(u >> 16);
+}
 
 // batch: a second copy of the geometric (and material) records scaled by each mesh's time
 // step, read by the RK stages (the right-hand side is linear in them).
 // nscat: scatterer faces (scattered-field form): an incident record and Nfp phases per face,
 // always in double.
-Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool batch = false,
-                   int64_t nscat = 0) {
+Layout make_layout(int K, int N, int Np, int Nfp, int prec, bool material, bool batch = false,
+                   int64_t nscat = 0, int tile_id = 0) {
+  const size_t ts = prec == DG_F64 ? 8 : 4;
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -76,7 +109,7 @@ Layout make_layout(int K, int N, int Np, int Nfp, size_t ts, bool material, bool
   L.off_elem_of = take(size_t(K) * sizeof(int32_t));
   L.off_pos_of = take(size_t(K) * sizeof(int32_t));
   L.off_partial = take(size_t((K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems) * sizeof(double));
-  L.opcat_bytes = size_t(opfrag_words_for(N, ts)) * ts;
+  L.opcat_bytes = opfrag_bytes_for(N, prec, tile_id);
   L.off_opcat = take(L.opcat_bytes);
   L.mat_bytes = material ? size_t(K) * dgh::kMatStride * ts : 0;
   L.off_mat = take(L.mat_bytes);
@@ -105,9 +138,19 @@ int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
   if (!mesh->vxyz || !mesh->etov) return fail(DG_E_ARG, "vxyz and etov must not be NULL");
   if (mesh->K <= 0 || mesh->nverts < 4) return fail(DG_E_ARG, "empty mesh");
   if (opts->order < 1 || opts->order > 7) return fail(DG_E_UNSUPPORTED, "order must be in 1..7");
-  if (opts->precision != DG_F64 && opts->precision != DG_F32)
+  if (opts->precision != DG_F64 && opts->precision != DG_F32 && opts->precision != DG_BF16X3)
     return fail(DG_E_UNSUPPORTED, "unknown precision");
+  if (opts->precision == DG_BF16X3 && !dgk::bf16x3_order(opts->order))
+    return fail(DG_E_UNSUPPORTED, "the split-BF16 contraction serves orders 5..7");
   if (opts->reorder < 0 || opts->reorder > 1) return fail(DG_E_ARG, "reorder must be 0 or 1");
+  if (opts->checks < 0) return fail(DG_E_ARG, "checks must be >= 0");
+  if (opts->tile_id < 0 || opts->tile_id > 2) return fail(DG_E_ARG, "tile_id must be 0, 1 or 2");
+  if (opts->tile_id == 2 && !contraction_kernel(opts->order, opts->precision))
+    return fail(DG_E_UNSUPPORTED, "no contraction kernel for this order and precision");
+  if (opts->tile_id == 1 && (opts->precision == DG_BF16X3 ||
+                             (opts->precision == DG_F32 && dgk::row_stride(opts->order, false) !=
+                                                               (opts->order + 1) * (opts->order + 2) * (opts->order + 3) / 6)))
+    return fail(DG_E_UNSUPPORTED, "no element-wise kernel for this order and precision");
   return DG_OK;
 }
 
@@ -138,6 +181,7 @@ struct dg_handle {
   // step (the device keeps the same value in the incident record; both add dt per step)
   int64_t nscat = 0;
   double t = 0.0;
+  int checks = 0;   // numeric monitor interval of dg_solve (0: off)
 
   bool f64() const { return prec == DG_F64; }
   void* at(size_t off) const { return ws + off; }
@@ -205,10 +249,30 @@ int upload(dg_handle* h, hipStream_t s) {
   for (const auto* m : {&R.Dr, &R.Ds, &R.Dt, &R.M}) ops.insert(ops.end(), m->begin(), m->end());
   ops.insert(ops.end(), R.LIFT.begin(), R.LIFT.end());
   std::vector<char> geo_b = to_prec(geo, h->f64()), ops_b = to_prec(ops, h->f64());
-  if (h->lay.opcat_bytes) {
+  if (h->lay.opcat_bytes && h->prec == DG_BF16X3) {
+    // [Dr | Ds | Dt | LIFT] split once in FP64: hi = bf16(x), lo = bf16(x - hi)
+    const int Np = h->Np, Nf4 = 4 * h->Nfp;
+    std::vector<uint16_t> ob(size_t(dgk::bopcat_words(h->N)), 0);
+    for (size_t w = 0; w < ob.size(); ++w) {
+      int n = -1, blk = -1, col = -1, part = -1;
+      dgk::bopfrag_source(h->N, int(w), &n, &blk, &col, &part);
+      if (n < 0 || blk < 0 || blk > 3 || col < 0 || part < 0) return fail(DG_E_ARG, "internal: bad operator map");
+      double x = 0.0;
+      if (n < Np && blk < 3 && col < Np) {
+        const std::vector<double>& Dm = blk == 0 ? R.Dr : blk == 1 ? R.Ds : R.Dt;
+        x = Dm[size_t(n) * Np + col];
+      } else if (n < Np && blk == 3 && col < Nf4) {
+        x = R.LIFT[size_t(n) * Nf4 + col];
+      }
+      const double hi = round_bf16(x);
+      ob[w] = bf16_bits(part == 0 ? hi : round_bf16(x - hi));
+    }
+    HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_opcat), ob.data(), ob.size() * 2, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else if (h->lay.opcat_bytes) {
     // OpCat = [Dr | Ds | Dt | LIFT] in the lane order of the contraction kernel
     const int Np = h->Np, Nf4 = 4 * h->Nfp;
-    std::vector<double> oc(size_t(opfrag_words_for(h->N, h->ts)), 0.0);
+    std::vector<double> oc(size_t(dgk::opcat_words(h->N)), 0.0);
     for (size_t w = 0; w < oc.size(); ++w) {
       int n = -1, blk = -1, col = -1;
       dgk::opfrag_source(h->N, int(w), &n, &blk, &col);
@@ -281,6 +345,7 @@ int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, 
   args.a = a;
   args.b = b;
   args.dt = dt;
+  args.split_bf16 = h->prec == DG_BF16X3;
   if (h->nscat) {
     args.src.rec = static_cast<const double*>(h->at(h->lay.off_src));
     args.src.phase = static_cast<const double*>(h->at(h->lay.off_phase));
@@ -380,8 +445,8 @@ int dg_setup_query(const dg_mesh* mesh, const dg_opts* opts, size_t* workspace_b
   if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
   const int N = opts->order;
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
-  *workspace_bytes = make_layout(mesh->K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4, mesh->eps || mesh->mu,
-                                 false, count_scatterers(mesh)).total;
+  *workspace_bytes = make_layout(mesh->K, N, Np, Nfp, opts->precision, mesh->eps || mesh->mu, false,
+                                 count_scatterers(mesh), opts->tile_id).total;
   return DG_OK;
 }
 
@@ -436,9 +501,10 @@ int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32
   h->ts = h->f64() ? 8 : 4;
   h->S = dgk::row_stride(h->N, h->f64());
   h->device = opts->device;
+  h->checks = opts->checks;
   h->nscat = int64_t(h->mesh.scat_face.size());
   if (h->nscat && h->batch) return fail(DG_E_UNSUPPORTED, "scatterer faces are not supported in a batch");
-  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->ts, !h->mat.empty(), h->batch, h->nscat);
+  h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->prec, !h->mat.empty(), h->batch, h->nscat, opts->tile_id);
   if (h->device >= 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());
@@ -469,6 +535,64 @@ int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32
     }
   }
   *out = h.release();
+  return DG_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// nsteps RK steps from the captured two-step graph of the current ping-pong parity (captured on
+// first use or when dt changes), plus one plain step for an odd count; advances the host clock.
+int solve_launch(dg_handle* h, double dt, int64_t nsteps, hipStream_t s) {
+  if (nsteps >= 2) {
+    // Two steps (ten stages) return the ping-pong state buffers to their starting roles, so
+    // one captured graph per starting parity replays any even number of steps.
+    const int p = h->cur;
+    if (!h->gexec[p] || h->graph_dt[p] != dt) {
+      h->drop_graph(p);
+      const int saved = h->cur;
+      HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      int r1 = rk_step_launch(h, dt, h->cap_stream);
+      int r2 = r1 ? r1 : rk_step_launch(h, dt, h->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+      h->cur = saved;
+      if (r2) {
+        if (g) (void)hipGraphDestroy(g);
+        return r2;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      h->graph[p] = g;
+      HIP_TRY(hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0));
+      h->graph_dt[p] = dt;
+    }
+    for (int64_t i = 0; i + 1 < nsteps; i += 2) {
+      HIP_TRY(hipGraphLaunch(h->gexec[p], s));
+      h->t += dt;
+      h->t += dt;
+    }
+  }
+  if (nsteps % 2) {
+    int rc = rk_step_launch(h, dt, s);
+    if (!rc) h->t += dt;
+    return rc;
+  }
+  return DG_OK;
+}
+
+// Energy of the state, summed on the host in block order (synchronises s).
+int energy_sync(const dg_handle* h, hipStream_t s, double* energy) {
+  const int nb = (h->K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems;
+  double* partial = static_cast<double*>(h->at(h->lay.off_partial));
+  HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo),
+                             h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr, h->K, partial, s));
+  std::vector<double> host(nb);
+  HIP_TRY(hipMemcpyAsync(host.data(), partial, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double e = 0.0;
+  for (double v : host) e += v;
+  *energy = e;
   return DG_OK;
 }
 
@@ -599,38 +723,26 @@ int dg_solve(dg_handle* h, double dt, int64_t nsteps, void* stream) {
   rc = set_device(h);
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (nsteps >= 2) {
-    // Two steps (ten stages) return the ping-pong state buffers to their starting roles, so
-    // one captured graph per starting parity replays any even number of steps.
-    const int p = h->cur;
-    if (!h->gexec[p] || h->graph_dt[p] != dt) {
-      h->drop_graph(p);
-      const int saved = h->cur;
-      HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-      int r1 = rk_step_launch(h, dt, h->cap_stream);
-      int r2 = r1 ? r1 : rk_step_launch(h, dt, h->cap_stream);
-      hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
-      h->cur = saved;
-      if (r2) {
-        if (g) (void)hipGraphDestroy(g);
-        return r2;
-      }
-      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      h->graph[p] = g;
-      HIP_TRY(hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0));
-      h->graph_dt[p] = dt;
-    }
-    for (int64_t i = 0; i + 1 < nsteps; i += 2) {
-      HIP_TRY(hipGraphLaunch(h->gexec[p], s));
-      h->t += dt;
-      h->t += dt;
-    }
-  }
-  if (nsteps % 2) {
-    rc = rk_step_launch(h, dt, s);
-    if (!rc) h->t += dt;
-    return rc;
+  if (h->checks <= 0 || nsteps == 0) return solve_launch(h, dt, nsteps, s);
+  // numeric monitor: chunks of `checks` steps, each followed by an energy check
+  double e0 = 0.0;
+  rc = energy_sync(h, s, &e0);
+  if (rc) return rc;
+  if (!std::isfinite(e0)) return fail(DG_E_NUMERIC, "non-finite energy before the first step");
+  const double tol = h->f64() ? 1e-10 : 1e-4;
+  for (int64_t done = 0; done < nsteps;) {
+    const int64_t n = std::min<int64_t>(h->checks, nsteps - done);
+    rc = solve_launch(h, dt, n, s);
+    if (rc) return rc;
+    done += n;
+    double e1 = 0.0;
+    rc = energy_sync(h, s, &e1);
+    if (rc) return rc;
+    if (!std::isfinite(e1))
+      return fail(DG_E_NUMERIC, "non-finite energy after " + std::to_string(done) + " steps");
+    if (h->nscat == 0 && e1 > e0 * (1.0 + tol))
+      return fail(DG_E_NUMERIC, "energy grew from " + std::to_string(e0) + " to " + std::to_string(e1) + " in " +
+                                    std::to_string(done) + " steps");
   }
   return DG_OK;
 }
@@ -641,18 +753,7 @@ int dg_energy(const dg_handle* h, double* energy, void* stream) {
   if (!energy) return fail(DG_E_ARG, "NULL energy");
   rc = set_device(h);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nb = (h->K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems;
-  double* partial = static_cast<double*>(h->at(h->lay.off_partial));
-  HIP_TRY(dgk::launch_energy(h->N, h->f64(), h->u(h->cur), h->ops().M, h->at(h->lay.off_geo),
-                             h->lay.mat_bytes ? h->at(h->lay.off_mat) : nullptr, h->K, partial, s));
-  std::vector<double> host(nb);
-  HIP_TRY(hipMemcpyAsync(host.data(), partial, nb * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  double e = 0.0;
-  for (double v : host) e += v;
-  *energy = e;
-  return DG_OK;
+  return energy_sync(h, static_cast<hipStream_t>(stream), energy);
 }
 
 int dg_energy_noalloc(const dg_handle* h, double* energy_dev, void* stream) {
@@ -750,8 +851,7 @@ int dg_setup_query_batch(const dg_mesh* meshes, int32_t count, const dg_opts* op
   if (!workspace_bytes) return fail(DG_E_ARG, "workspace_bytes must not be NULL");
   const int N = opts->order;
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
-  *workspace_bytes = make_layout(c.m.K, N, Np, Nfp, opts->precision == DG_F64 ? 8 : 4,
-                                 c.m.eps != nullptr, true).total;
+  *workspace_bytes = make_layout(c.m.K, N, Np, Nfp, opts->precision, c.m.eps != nullptr, true, 0, opts->tile_id).total;
   return DG_OK;
 }
 
@@ -820,6 +920,125 @@ int dg_set_batch_dt(dg_handle* h, const double* dt, void* stream) {
     HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_mat_dt), mat_b.data(), mat_b.size(), hipMemcpyHostToDevice, s));
   }
   HIP_TRY(hipStreamSynchronize(s));   // host staging buffers die at return
+  return DG_OK;
+}
+
+}  // extern "C"
+
+struct dg_group {
+  std::vector<dg_handle*> m;
+  int device = 0;
+  hipStream_t cap = nullptr;               // the capture's origin stream
+  std::vector<hipEvent_t> ev;              // fork event, then one join event per member
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int> parity;                 // members' ping-pong parity at capture
+  std::vector<double> dt;                  // members' steps at capture
+  void drop() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
+};
+
+extern "C" {
+
+int dg_group_create(dg_handle* const* members, int32_t count, dg_group** out) {
+  if (out) *out = nullptr;
+  if (!out || !members || count < 1) return fail(DG_E_ARG, "a group needs at least one member");
+  std::unique_ptr<dg_group> g(new (std::nothrow) dg_group);
+  if (!g) return fail(DG_E_OOM, "host allocation failed");
+  for (int32_t i = 0; i < count; ++i) {
+    dg_handle* h = members[i];
+    int rc = need_device(h);
+    if (rc) return rc;
+    if (i && h->device != members[0]->device) return fail(DG_E_ARG, "group members must share a device");
+    for (int32_t j = 0; j < i; ++j)
+      if (members[j] == h) return fail(DG_E_ARG, "a handle appears twice in the group");
+    g->m.push_back(h);
+  }
+  g->device = members[0]->device;
+  int rc = set_device(members[0]);
+  if (rc) return rc;
+  g->ev.assign(size_t(count) + 1, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+  for (auto& x : g->ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    for (auto& x : g->ev)
+      if (x) (void)hipEventDestroy(x);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    return hip_fail(e, "dg_group_create");
+  }
+  *out = g.release();
+  return DG_OK;
+}
+
+int dg_group_free(dg_group* g) {
+  if (!g) return DG_OK;
+  (void)hipSetDevice(g->device);
+  g->drop();
+  for (auto& x : g->ev)
+    if (x) (void)hipEventDestroy(x);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  delete g;
+  return DG_OK;
+}
+
+int dg_group_solve(dg_group* g, const double* dt, int64_t nsteps, void* stream) {
+  if (!g || !dt || nsteps < 0) return fail(DG_E_ARG, "bad group, dt or nsteps");
+  const size_t n = g->m.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(dt[i])) return fail(DG_E_ARG, "dt must be finite");
+  HIP_TRY(hipSetDevice(g->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (nsteps >= 2) {
+    bool same = g->gexec != nullptr;
+    for (size_t i = 0; i < n && same; ++i) same = g->parity[i] == g->m[i]->cur && g->dt[i] == dt[i];
+    if (!same) {
+      g->drop();
+      std::vector<int> saved(n);
+      for (size_t i = 0; i < n; ++i) saved[i] = g->m[i]->cur;
+      HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+      int rc = 0;
+      hipError_t e = hipEventRecord(g->ev[0], g->cap);
+      for (size_t i = 0; i < n && !rc && e == hipSuccess; ++i) {
+        dg_handle* h = g->m[i];
+        e = hipStreamWaitEvent(h->cap_stream, g->ev[0], 0);
+        if (e != hipSuccess) break;
+        rc = rk_step_launch(h, dt[i], h->cap_stream);
+        if (!rc) rc = rk_step_launch(h, dt[i], h->cap_stream);
+        if (!rc) e = hipEventRecord(g->ev[i + 1], h->cap_stream);
+        if (!rc && e == hipSuccess) e = hipStreamWaitEvent(g->cap, g->ev[i + 1], 0);
+      }
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
+      for (size_t i = 0; i < n; ++i) g->m[i]->cur = saved[i];
+      if (rc || e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+        return hip_fail(e != hipSuccess ? e : e2, "group capture");
+      }
+      g->graph = graph;
+      HIP_TRY(hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0));
+      g->parity = saved;
+      g->dt.assign(dt, dt + n);
+    }
+    for (int64_t k = 0; k + 1 < nsteps; k += 2) {
+      HIP_TRY(hipGraphLaunch(g->gexec, s));
+      for (size_t i = 0; i < n; ++i) {
+        g->m[i]->t += dt[i];
+        g->m[i]->t += dt[i];
+      }
+    }
+  }
+  if (nsteps % 2)
+    for (size_t i = 0; i < n; ++i) {
+      int rc = rk_step_launch(g->m[i], dt[i], s);
+      if (rc) return rc;
+      g->m[i]->t += dt[i];
+    }
   return DG_OK;
 }
 

@@ -1087,6 +1087,669 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// MFMA form of the fused stage in FP64 (N = 3).
+//
+// The same contraction as the FP32 kernels (contravariant fluxes; rhs = OpCat x [G; Fscale/2
+// flux]; k-steps in volume quads, face quads and volume singles; the operator table in the
+// same fragment order), on v_mfma_f64_16x16x4f64. On gfx950 the FP64 matrix rate equals the
+// FP64 vector rate (64 cycles per 16x16x4 step), so the point of the matrix path is that
+// the multiply-adds leave the VALU free for the operand, the fluxes and the memory phases.
+// The Np mod 16 tail columns run on v_mfma_f64_4x4x4f64, whose A operand has the lane layout
+// of the 16x16x4 one (lane 16 k + 4 b + r holds row 4 b + r of k-step k): it takes the same
+// operand register, and its B operand (lane 16 k + 4 b + c) is the tail operator replicated
+// over the four row blocks b, which is the (k-group, column) order of the FP32 tail table.
+// Result layouts: 16x16x4, lane (li, g4) register i = row g4 + 4 i, column li; 4x4x4, lane
+// (li, g4) = row 4 (li / 4) + g4, column li mod 4.
+//
+// One wave per field: a tile of 16 elements has six 16-row tiles (field f, element li), and
+// wave f computes all column tiles and the tail of row tile f, so the six waves carry equal
+// matrix work. Fields, fluxes and the operator table sit in LDS; the next tile's fields,
+// geometry and exterior traces are loaded into registers during this tile, every load issued
+// on every path with clamped indices (as in the FP32 kernels).
+template <int N>
+struct DDims {
+  using M = MDims<N>;                                 // operand and operator geometry
+  static constexpr int Np = M::Np, Nfp = M::Nfp, Nf4 = M::Nf4;
+  static constexpr int E = 16;                        // elements per tile
+  static constexpr int WAVES = 6, THREADS = 64 * WAVES;
+  static constexpr int NPP = M::NPP;                  // row stride of the field arrays
+  static constexpr int ES = 6 * NPP + 2;              // element stride in LDS (doubles, = 2 mod 4)
+  static constexpr int NF = M::NF, RSL = NF + 2;      // flux row stride (doubles, = 2 mod 4)
+  static constexpr int KS = M::KS, VB = M::VB, VR = M::VR, QV = M::QV, QF = M::QF, NQ = M::NQ;
+  static constexpr int NT = M::NT, TAIL = M::TAIL;
+  static constexpr int TW = E * 6 * NPP;              // doubles per tile
+  static constexpr int TC = TW / 2;                   // 16-byte chunks per tile
+  static constexpr int CPT = (TC + THREADS - 1) / THREADS;
+  static constexpr int FIT = (E * Nf4 + THREADS - 1) / THREADS;
+  static constexpr int OPC = M::OPC;
+  static_assert(NPP == Np, "FP64 rows are unpadded");
+  static_assert((6 * NPP) % 2 == 0, "16-byte chunks do not straddle elements");
+  static_assert(TAIL > 0 && TAIL <= 4, "one 4x4x4 tail block");
+  static_assert(E * ES <= 6 * E * RSL, "staging fits in the flux rows");
+};
+
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+__global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void dmfma_stage_kernel(
+    const double* __restrict__ u_in, double* __restrict__ out, double* __restrict__ res,
+    const double* __restrict__ geo, const int32_t* __restrict__ fcode, const double* __restrict__ mat,
+    const double* __restrict__ opf, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, double ca, double cb, double cdt, SrcArgs inc) {
+  using D = DDims<N>;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES, NF = D::NF,
+                KS = D::KS, RSL = D::RSL, NT = D::NT, TAIL = D::TAIL, FIT = D::FIT, TC = D::TC, CPT = D::CPT,
+                VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF, NQ = D::NQ, NTH = D::THREADS;
+  constexpr int G = dgh::kGeoStride;
+  constexpr int GW = E * G;
+  constexpr int GPT = (GW + NTH - 1) / NTH;
+  __shared__ __align__(16) double up_s[E * ES];            // field tile [e][f][n]
+  __shared__ __align__(16) double gl[6 * E * RSL];         // flux rows [f E + e][fj]; later staging
+  __shared__ __align__(16) double bfs[NT * KS * 64];       // operator fragments
+  __shared__ __align__(16) double tops[KS * 16];           // tail operator (k-group, column)
+  __shared__ double gt[GW];
+  __shared__ __align__(16) double wmat[MAT ? E * 4 * dgh::kMatFace : 2];   // MAT: [e][f][A B C D]
+  __shared__ int32_t fcb[2][E * 4];
+  __shared__ uint8_t nbr_s[96 * NFP];
+  __shared__ uint8_t fm_s[4 * NFP];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int fw = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's field (row tile)
+  const int g4 = lane >> 4, li = lane & 15;
+  auto slot = [](int q) __attribute__((always_inline)) {
+    const int e = q / (6 * NPP);
+    return e * ES + (q - e * 6 * NPP);
+  };
+
+  const int nwg = gridDim.x / kXcds;
+  const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
+  const int TX = (ntiles + kXcds - 1) / kXcds;
+  const int tend = min(ntiles, (xcd + 1) * TX);
+  int tile = xcd * TX + wj;
+  if (tile >= tend) return;
+
+  for (int q = tid; q < NT * KS * 64; q += NTH) bfs[q] = opf[q];
+  for (int q = tid; q < KS * 16; q += NTH) tops[q] = opf[NT * KS * 64 + q];
+  for (int q = tid; q < 96 * NFP; q += NTH) nbr_s[q] = uint8_t(nbrnode[q]);
+  for (int q = tid; q < 4 * NFP; q += NTH) fm_s[q] = uint8_t(fmask[q]);
+  for (int q = tid; q < E * ES; q += NTH) up_s[q] = 0.0;
+  __syncthreads();
+
+  int tq = tid;
+  if (MAT) asm volatile("" : "+v"(tq));
+  doublex2 pu[CPT];
+  double pg[GPT];
+  double nup[FIT][6];
+  int32_t pf = 0;
+  double pm = 0.0, pw = 0.0;
+  const size_t fc_last = size_t(K) * 4 - 1;
+  const size_t chunk_last = size_t(K) * 6 * NPP / 2 - 1;
+  const doublex2* u2 = reinterpret_cast<const doublex2*>(u_in);
+  auto prefetch = [&](int t) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) pu[r] = u2[min(size_t(t) * TC + min(tid + r * NTH, TC - 1), chunk_last)];
+#pragma unroll
+    for (int r = 0; r < GPT; ++r)
+      pg[r] = geo[min(size_t(t) * GW + min(tid + r * NTH, GW - 1), size_t(K) * G - 1)];
+    if (MAT) {
+      const int q = min(tid, 2 * E - 1);
+      const size_t e = min(size_t(t) * E + q / 2, size_t(K) - 1);
+      pm = mat[e * dgh::kMatStride + (q & 1)];
+      const int qw = min(tid, 16 * E - 1);
+      const size_t ew = min(size_t(t) * E + qw / 16, size_t(K) - 1);
+      pw = mat[ew * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
+    }
+    pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+  };
+  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+    const int e0 = t * E, nl = min(E, K - e0);
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = min(tq + r * NTH, nl * NF4 - 1);
+      const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+      const int code = fcv[e * 4 + f];
+      const int ci = code >= 0 ? code : 0;
+      const int nn = nbr_s[((f * 4 + (ci & 3)) * 6 + ((ci >> 2) & 7)) * NFP + j];
+      const double* p = u_in + (code >= 0 ? size_t(ci >> 5) * 6 * NPP + nn : size_t(e0 + e) * 6 * NPP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nup[r][c] = p[c * NPP];
+    }
+  };
+  int par = 0;
+  if (tid < E * 4) {
+    fcb[0][tid] = fcode[min(size_t(tile) * E * 4 + tid, fc_last)];
+    fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
+  }
+  __syncthreads();
+  gather(tile, fcb[0]);
+  prefetch(tile);
+  pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+
+  for (; tile < tend; tile += nwg) {
+    const int base = tile * E;
+    const int nel = min(E, K - base);
+    const bool full = nel == E;
+    const size_t tb = size_t(base) * 6 * NPP;
+    const bool more = tile + nwg < tend;
+    const int nxt = more ? tile + nwg : tile;
+
+    // ---- tile into LDS
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if ((r + 1) * NTH <= TC || c < TC) *reinterpret_cast<doublex2*>(up_s + slot(2 * c)) = pu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < GW) gt[q] = pg[r];
+      }
+      if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * E) wmat[tid] = pw;
+    } else {
+      for (int q = tid; q < nel * 6 * NPP; q += NTH) up_s[slot(q)] = u_in[tb + q];
+      if (MAT) {
+        for (int q = tid; q < 2 * nel; q += NTH)
+          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+        for (int q = tid; q < 16 * nel; q += NTH)
+          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      }
+      for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
+    }
+    __syncthreads();
+
+    // ---- face fluxes from the exterior traces gathered during the previous tile
+    const int32_t* fc = fcb[par];
+    {
+      if constexpr (NF > NF4)
+        for (int q = tid; q < 6 * E * (NF - NF4); q += NTH) {
+          const int row = q / (NF - NF4);
+          gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tq + r * NTH;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          const double* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+          const double nx = g[0], ny = g[1], nz = g[2], hs = 0.5 * g[3];
+          const double* um = up_s + e * ES + fm_s[f * NFP + j];
+          double m[6], d[6], w[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int c = 0; c < 6; ++c) m[c] = um[c * NPP];
+          const int code = fc[e * 4 + f];
+          if (SRC && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
+          face_jump(code, m, nup[r], d);
+          if (MAT) {
+            const doublex2 w01 = *reinterpret_cast<const doublex2*>(wmat + 16 * e + 4 * f);
+            const doublex2 w23 = *reinterpret_cast<const doublex2*>(wmat + 16 * e + 4 * f + 2);
+            w[0] = w01.x, w[1] = w01.y, w[2] = w23.x, w[3] = w23.y;
+          }
+          upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
+        }
+      }
+    }
+    __syncthreads();
+    doublex2 rs[CPT];
+    if (STAGE) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r)
+        rs[r] = reinterpret_cast<const doublex2*>(res)[min(size_t(tile) * TC + min(tid + r * NTH, TC - 1), chunk_last)];
+    }
+    // the next tile's fields and geometry, then its exterior traces
+    prefetch(nxt);
+    gather(nxt, fcb[more ? par ^ 1 : par]);
+
+    // ---- contraction of row tile fw (field fw, element li)
+    doublex4 acc[NT];
+    double tacc = 0.0;
+    {
+      const int a = fw % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+      const int srcf = fw < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
+      const double sg = fw < 3 ? 1.0 : -1.0;
+      const double* cm = gt + li * G;
+      const double sm = MAT ? sg * up_s[li * ES + 6 * NPP + (fw < 3 ? 0 : 1)] : sg;
+      double pc[3], qc[3];   // operand = pc[mu] V_c + qc[mu] V_b
+#pragma unroll
+      for (int mu = 0; mu < 3; ++mu) {
+        pc[mu] = sm * cm[3 * mu + b];
+        qc[mu] = -sm * cm[3 * mu + c];
+      }
+      const double* vc = up_s + li * ES + (srcf + c) * NPP;
+      const double* vb = up_s + li * ES + (srcf + b) * NPP;
+      const double* fl = gl + (fw * E + li) * RSL + 4 * g4;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+      auto ld4 = [](const double* p) __attribute__((always_inline)) {
+        const doublex2 lo = *reinterpret_cast<const doublex2*>(p);
+        const doublex2 hi = *reinterpret_cast<const doublex2*>(p + 2);
+        return doublex4{lo.x, lo.y, hi.x, hi.y};
+      };
+      const double* bq = bfs + 4 * lane;                  // quad q of column tile t: bq + (t KS + 4 q) 64
+      const double* bs = bfs + NQ * 256 + lane;           // single s of column tile t: bs + t KS 64 + 64 s
+      const int tl = 4 * g4 + (li & 3);
+      const double* tq4 = tops + 4 * tl;                  // tail quad q: tq4 + 64 q
+      const double* ts1 = tops + NQ * 64 + tl;            // tail single s: ts1 + 16 s
+      auto step = [&](double av, const doublex4 (&w)[NT], const doublex4& z, int s) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, w[t][s], acc[t], 0, 0, 0);
+        tacc = __builtin_amdgcn_mfma_f64_4x4x4f64(av, z[s], tacc, 0, 0, 0);
+      };
+#pragma unroll
+      for (int jb = 0; jb < VB; ++jb) {
+        const doublex4 xc = ld4(vc + 16 * jb + 4 * g4);
+        const doublex4 xb = ld4(vb + 16 * jb + 4 * g4);
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const int q = 3 * jb + mu;
+          doublex4 w[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) w[t] = ld4(bq + (t * KS * 64) + 256 * q);
+          const doublex4 z = ld4(tq4 + 64 * q);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) step(pc[mu] * xc[s] + qc[mu] * xb[s], w, z, s);
+        }
+      }
+#pragma unroll
+      for (int fb = 0; fb < QF; ++fb) {
+        const int q = QV + fb;
+        const doublex4 xf = ld4(fl + 16 * fb);
+        doublex4 w[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t] = ld4(bq + (t * KS * 64) + 256 * q);
+        const doublex4 z = ld4(tq4 + 64 * q);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) step(xf[s], w, z, s);
+      }
+#pragma unroll
+      for (int r = 0; r < VR; ++r) {
+        const double xc1 = vc[16 * VB + 4 * r + g4];   // columns >= Np read the zero padding
+        const double xb1 = vb[16 * VB + 4 * r + g4];
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const int sgl = 3 * r + mu;
+          const double av = pc[mu] * xc1 + qc[mu] * xb1;
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bs[t * KS * 64 + 64 * sgl], acc[t], 0, 0, 0);
+          tacc = __builtin_amdgcn_mfma_f64_4x4x4f64(av, ts1[16 * sgl], tacc, 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();   // flux rows are read: reuse them for the staging
+
+    // ---- stage the right-hand side [e][f][n] (laid out like up_s)
+    double* stage = gl;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) stage[(g4 + 4 * i) * ES + fw * NPP + 16 * t + li] = acc[t][i];
+    if ((li & 3) < TAIL) stage[(4 * (li >> 2) + g4) * ES + fw * NPP + 16 * NT + (li & 3)] = tacc;
+    __syncthreads();
+
+    // ---- update and write out, 16-byte chunks
+    if (full) {
+      doublex2* o2 = reinterpret_cast<doublex2*>(out + tb);
+      doublex2* r2 = reinterpret_cast<doublex2*>(res + tb);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if ((r + 1) * NTH <= TC || c < TC) {
+          const int o = slot(2 * c);
+          const doublex2 h = *reinterpret_cast<const doublex2*>(stage + o);
+          if (STAGE) {
+            const doublex2 u = *reinterpret_cast<const doublex2*>(up_s + o);
+            const doublex2 rv = doublex2{ca * rs[r].x + cdt * h.x, ca * rs[r].y + cdt * h.y};
+            r2[c] = rv;
+            o2[c] = doublex2{u.x + cb * rv.x, u.y + cb * rv.y};
+          } else {
+            o2[c] = h;
+          }
+        }
+      }
+    } else {
+      for (int q = tid; q < nel * 6 * NPP; q += NTH) {
+        const double h = stage[slot(q)];
+        if (STAGE) {
+          const double rv = ca * res[tb + q] + cdt * h;
+          res[tb + q] = rv;
+          out[tb + q] = up_s[slot(q)] + cb * rv;
+        } else {
+          out[tb + q] = h;
+        }
+      }
+    }
+    if (tile + 2 * nwg < tend && tid < E * 4) fcb[par][tid] = pf;
+    par ^= 1;
+    __syncthreads();   // the next tile overwrites up_s, gt, fcb and gl
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Split-BF16 form of the FP32 contraction (N = 5, 6, 7): each value x of the operand and of
+// the operator is carried as x_hi + x_lo, x_hi = bf16(x), x_lo = bf16(x - x_hi), and a
+// product is taken as x_hi y_hi + x_hi y_lo + x_lo y_hi (three v_mfma_f32_16x16x32_bf16 per
+// 32-deep k-block, FP32 accumulation). Per product the error is about 3 * 2^-18 |x y| (the
+// dropped x_lo y_lo and the two splitting residuals), so the result carries about 1e-5 of
+// the absolute sum of its terms; the state, the fluxes and the RK update stay FP32.
+//
+// k-axis of one element row: [D_r | D_s | D_t] blocks of NP8 = roundup(Np, 8) nodes, then the
+// face block of NF8 = roundup(4 Nfp, 8) face nodes, zero-padded to KD = roundup(., 32). Lane
+// (li, g4) of a 16x16x32 step holds k-values 32 b + 8 g4 .. + 7 of row li, which lie in one
+// block. The operator is split once on the host and kept in VGPRs (8 per k-block and lane);
+// the operand is formed once per tile, for all column tiles, and stored split in LDS:
+//   volume columns (mu, n): pc[mu] V_c[n] + qc[mu] V_b[n] (the contravariant flux, as in the
+//   FP32 kernels), face columns: the Fscale-scaled upwind flux, written by the flux phase.
+// Tile, waves and memory phases follow the FP32 kernel for these orders: 8 elements (three
+// 16-row tiles), one wave per 16-node column tile.
+template <int N>
+struct BDims {
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, Nf4 = Dims<N>::Nf4;
+  static constexpr int E = 8, ROWS = 6 * E, RT = ROWS / 16;
+  static constexpr int NT = (Np + 15) / 16, THREADS = 64 * NT;
+  static constexpr int NPP = Np;                      // field rows (Np % 4 == 0 at these orders)
+  static constexpr int ES = 6 * NPP + 4;
+  static constexpr int NP8 = (Np + 7) / 8 * 8, KV = 3 * NP8;
+  static constexpr int NF8 = (Nf4 + 7) / 8 * 8;
+  static constexpr int KD = (KV + NF8 + 31) / 32 * 32, KB = KD / 32;
+  static constexpr int AS = KD + 8;                   // operand row stride (bf16), rows 16 B aligned
+  static constexpr int VG = KV / 8;                   // 8-column volume groups per row
+  static constexpr int TW = E * 6 * Np, TW4 = TW / 4;
+  static constexpr int CPT = (TW4 + THREADS - 1) / THREADS;
+  static constexpr int FIT = (E * Nf4 + THREADS - 1) / THREADS;
+  static constexpr int OPW = NT * KB * 64 * 16;       // operator table, bf16 words
+  static_assert(Np % 4 == 0, "16-byte chunks of a tile map to the LDS rows");
+  static_assert(2 * TW <= ROWS * AS, "staging fits in the low-part array");
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+__global__ __launch_bounds__(BDims<N>::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void bmfma_stage_kernel(
+    const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
+    const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
+    const uint16_t* __restrict__ opb, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt, SrcArgs inc) {
+  using D = BDims<N>;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES, RT = D::RT,
+                NP8 = D::NP8, KV = D::KV, KD = D::KD, KB = D::KB, AS = D::AS, VG = D::VG, TW4 = D::TW4,
+                CPT = D::CPT, FIT = D::FIT, NTH = D::THREADS;
+  constexpr int G = dgh::kGeoStride;
+  constexpr int GW = E * G;
+  constexpr int GPT = (GW + NTH - 1) / NTH;
+  __shared__ __align__(16) float up_s[E * ES];             // field tile [e][f][n]
+  __shared__ __align__(16) __bf16 ahi[D::ROWS * AS];       // operand, high parts [f E + e][k]
+  __shared__ __align__(16) __bf16 alo[D::ROWS * AS];       // operand, low parts; later staging
+  __shared__ float gt[GW];
+  __shared__ __align__(16) float wmat[MAT ? E * 4 * dgh::kMatFace : 4];
+  __shared__ int32_t fcb[2][E * 4];
+  __shared__ uint8_t nbr_s[96 * NFP];
+  __shared__ uint8_t fm_s[4 * NFP];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's column tile
+  const int g4 = lane >> 4, li = lane & 15;
+  auto slot = [](int q) __attribute__((always_inline)) {
+    const int e = q / (6 * NP);
+    return e * ES + (q - e * 6 * NP);
+  };
+  auto split = [](float x, __bf16& h, __bf16& l) __attribute__((always_inline)) {
+    h = __bf16(x);
+    l = __bf16(x - float(h));
+  };
+
+  const int nwg = gridDim.x / kXcds;
+  const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
+  const int TX = (ntiles + kXcds - 1) / kXcds;
+  const int tend = min(ntiles, (xcd + 1) * TX);
+  int tile = xcd * TX + wj;
+  if (tile >= tend) return;
+
+  // once per workgroup: this wave's operator (high and low parts per k-block), node tables, the
+  // zero padding of the operand rows (face columns past 4 Nfp; never written afterwards)
+  bf16x8 bh[KB], bl[KB];
+  {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(opb) + size_t(nt) * KB * 64 * 2 + 2 * lane;
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      bh[b] = src[b * 128];
+      bl[b] = src[b * 128 + 1];
+    }
+  }
+  for (int q = tid; q < 96 * NFP; q += NTH) nbr_s[q] = uint8_t(nbrnode[q]);
+  for (int q = tid; q < 4 * NFP; q += NTH) fm_s[q] = uint8_t(fmask[q]);
+  for (int q = tid; q < D::ROWS * AS; q += NTH) {
+    ahi[q] = __bf16(0.f);
+    alo[q] = __bf16(0.f);
+  }
+
+  int tq = tid;
+  asm volatile("" : "+v"(tq));
+  floatx4 pu[CPT];
+  float pg[GPT];
+  float nup[FIT][6];
+  int32_t pf = 0;
+  float pm = 0.f, pw = 0.f;
+  const size_t fc_last = size_t(K) * 4 - 1;
+  const size_t chunk_last = size_t(K) * 6 * NP / 4 - 1;
+  const floatx4* u4 = reinterpret_cast<const floatx4*>(u_in);
+  auto prefetch = [&](int t) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) pu[r] = u4[min(size_t(t) * TW4 + min(tid + r * NTH, TW4 - 1), chunk_last)];
+#pragma unroll
+    for (int r = 0; r < GPT; ++r)
+      pg[r] = geo[min(size_t(t) * GW + min(tid + r * NTH, GW - 1), size_t(K) * G - 1)];
+    if (MAT) {
+      const int q = min(tid, 2 * E - 1);
+      const size_t e = min(size_t(t) * E + q / 2, size_t(K) - 1);
+      pm = mat[e * dgh::kMatStride + (q & 1)];
+      const int qw = min(tid, 16 * E - 1);
+      const size_t ew = min(size_t(t) * E + qw / 16, size_t(K) - 1);
+      pw = mat[ew * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
+    }
+    pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+  };
+  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+    const int e0 = t * E, nl = min(E, K - e0);
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = min(tq + r * NTH, nl * NF4 - 1);
+      const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+      const int code = fcv[e * 4 + f];
+      const int ci = code >= 0 ? code : 0;
+      const int nn = nbr_s[((f * 4 + (ci & 3)) * 6 + ((ci >> 2) & 7)) * NFP + j];
+      const float* p = u_in + (code >= 0 ? size_t(ci >> 5) * 6 * NP + nn : size_t(e0 + e) * 6 * NP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nup[r][c] = p[c * NP];
+    }
+  };
+  int par = 0;
+  if (tid < E * 4) {
+    fcb[0][tid] = fcode[min(size_t(tile) * E * 4 + tid, fc_last)];
+    fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
+  }
+  __syncthreads();
+  prefetch(tile);
+  pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+
+  for (; tile < tend; tile += nwg) {
+    const int base = tile * E;
+    const int nel = min(E, K - base);
+    const bool full = nel == E;
+    const size_t tb = size_t(base) * 6 * NP;
+    const bool more = tile + nwg < tend;
+    const int nxt = more ? tile + nwg : tile;
+
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < TW4) *reinterpret_cast<floatx4*>(up_s + slot(4 * q)) = pu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < GW) gt[q] = pg[r];
+      }
+      if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * E) wmat[tid] = pw;
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += NTH) up_s[slot(q)] = u_in[tb + q];
+      if (MAT) {
+        for (int q = tid; q < 2 * nel; q += NTH)
+          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+        for (int q = tid; q < 16 * nel; q += NTH)
+          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      }
+      for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
+    }
+    __syncthreads();
+
+    // ---- face fluxes, written split into the face columns of the operand rows; the face
+    // padding columns (their operator columns are zero) are cleared again, since the staging
+    // of the previous tile wrote over the low parts
+    const int32_t* fc = fcb[par];
+    gather(tile, fc);
+    if constexpr (KD > KV + NF4)
+      for (int q = tid; q < D::ROWS * (KD - KV - NF4); q += NTH) {
+        const int row = q / (KD - KV - NF4), col = KV + NF4 + (q - row * (KD - KV - NF4));
+        ahi[row * AS + col] = __bf16(0.f);
+        alo[row * AS + col] = __bf16(0.f);
+      }
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = tq + r * NTH;
+      if (q < nel * NF4) {
+        const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+        const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+        const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
+        const float* um = up_s + e * ES + fm_s[f * NFP + j];
+        float m[6], d[6], w[4] = {0.f, 0.f, 0.f, 0.f}, fl[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) m[c] = um[c * NPP];
+        const int code = fc[e * 4 + f];
+        if (SRC && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
+        face_jump(code, m, nup[r], d);
+        if (MAT) {
+          const floatx4 wv = *reinterpret_cast<const floatx4*>(wmat + 16 * e + 4 * f);
+          w[0] = wv.x, w[1] = wv.y, w[2] = wv.z, w[3] = wv.w;
+        }
+        upwind_flux(MAT, nx, ny, nz, hs, w, d, fl, 1);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) split(fl[c], ahi[(c * E + e) * AS + KV + fj], alo[(c * E + e) * AS + KV + fj]);
+      }
+    }
+    // ---- volume columns: the contravariant flux, eight nodes of one direction per item
+    for (int q = tid; q < D::ROWS * VG; q += NTH) {
+      const int row = q / VG, grp = q - row * VG;
+      const int f = row / E, e = row - f * E;
+      const int mu = (8 * grp) / NP8, n0 = 8 * grp - mu * NP8;
+      const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+      const int srcf = f < 3 ? 3 : 0;
+      const float sg = f < 3 ? 1.f : -1.f;
+      const float sm = MAT ? sg * up_s[e * ES + 6 * NPP + (f < 3 ? 0 : 1)] : sg;
+      const float pc = sm * gt[e * G + 3 * mu + b], qc = -sm * gt[e * G + 3 * mu + c];
+      const float* vc = up_s + e * ES + (srcf + c) * NPP + n0;
+      const float* vb = up_s + e * ES + (srcf + b) * NPP + n0;
+      const floatx4 c0 = *reinterpret_cast<const floatx4*>(vc), c1 = *reinterpret_cast<const floatx4*>(vc + 4);
+      const floatx4 b0 = *reinterpret_cast<const floatx4*>(vb), b1 = *reinterpret_cast<const floatx4*>(vb + 4);
+      const float xv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+      const float yv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+      bf16x8 h, l;
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        // nodes past Np (NP8 > Np) read the next row or the row padding: finite, and their
+        // operator columns are zero; they are stored as zero all the same
+        const float gv = n0 + jj < NP ? pc * xv[jj] + qc * yv[jj] : 0.f;
+        __bf16 hh, ll;
+        split(gv, hh, ll);
+        h[jj] = hh;
+        l[jj] = ll;
+      }
+      *reinterpret_cast<bf16x8*>(ahi + row * AS + 8 * grp) = h;
+      *reinterpret_cast<bf16x8*>(alo + row * AS + 8 * grp) = l;
+    }
+    floatx4 rs4[CPT];
+    if (STAGE) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r)
+        rs4[r] = reinterpret_cast<const floatx4*>(res)[min(size_t(tile) * TW4 + min(tid + r * NTH, TW4 - 1), chunk_last)];
+    }
+    prefetch(nxt);
+    __syncthreads();
+
+    // ---- contraction: three products per 32-deep k-block
+    floatx4 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int o = (16 * t + li) * AS + 32 * b + 8 * g4;
+        const bf16x8 xh = *reinterpret_cast<const bf16x8*>(ahi + o);
+        const bf16x8 xl = *reinterpret_cast<const bf16x8*>(alo + o);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bh[b], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bl[b], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bh[b], acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();   // the operand is read: reuse its low parts for the staging
+
+    // ---- stage the right-hand side [e][f][n]: lane (li, g4), register i = row 16 t + 4 g4 + i
+    float* stage = reinterpret_cast<float*>(alo);
+    const int col = 16 * nt + li;
+    if (col < NP) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * t + 4 * g4 + i;
+          const int f = row / E, e = row - f * E;
+          stage[(e * 6 + f) * NP + col] = acc[t][i];
+        }
+    }
+    __syncthreads();
+
+    if (full) {
+      floatx4* o4 = reinterpret_cast<floatx4*>(out + tb);
+      floatx4* r4 = reinterpret_cast<floatx4*>(res + tb);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < TW4) {
+          const floatx4 h = reinterpret_cast<const floatx4*>(stage)[q];
+          if (STAGE) {
+            const floatx4 u = *reinterpret_cast<const floatx4*>(up_s + slot(4 * q));
+            const floatx4 rv = ca * rs4[r] + cdt * h;
+            r4[q] = rv;
+            o4[q] = u + cb * rv;
+          } else {
+            o4[q] = h;
+          }
+        }
+      }
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += NTH) {
+        const float h = stage[q];
+        if (STAGE) {
+          const float rv = ca * res[tb + q] + cdt * h;
+          res[tb + q] = rv;
+          out[tb + q] = up_s[slot(q)] + cb * rv;
+        } else {
+          out[tb + q] = h;
+        }
+      }
+    }
+    if (tile + 2 * nwg < tend && tid < E * 4) fcb[par][tid] = pf;
+    par ^= 1;
+    __syncthreads();
+  }
+}
+
 // Resident workgroups for the persistent grid: CUs x workgroups per CU, a multiple of the XCD
 // count (queried once per kernel and device: the template argument is the kernel itself, so
 // every kernel keeps its own count).
@@ -1159,6 +1822,46 @@ template <int N, bool STAGE, bool MAT, bool SRC>
 struct HmfmaLaunch {
   static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
     return launch_hmfma_v<N, STAGE, MAT, SRC>(o, a, s);
+  }
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+hipError_t launch_dmfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const int E = DDims<N>::E;
+  const int ntiles = (a.K + E - 1) / E;
+  const int nb = persistent_grid<dmfma_stage_kernel<N, STAGE, MAT, SRC>>(DDims<N>::THREADS, ntiles);
+  dmfma_stage_kernel<N, STAGE, MAT, SRC><<<nb, DDims<N>::THREADS, 0, s>>>(
+      static_cast<const double*>(a.u_in), static_cast<double*>(a.out), static_cast<double*>(a.res),
+      static_cast<const double*>(a.geo), a.fcode, static_cast<const double*>(a.mat),
+      static_cast<const double*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
+      STAGE ? a.a : 0.0, STAGE ? a.b : 0.0, STAGE ? a.dt : 0.0, a.src);
+  return hipGetLastError();
+}
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+struct DmfmaLaunch {
+  static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
+    return launch_dmfma_v<N, STAGE, MAT, SRC>(o, a, s);
+  }
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+hipError_t launch_bmfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const int E = BDims<N>::E;
+  const int ntiles = (a.K + E - 1) / E;
+  const int nb = persistent_grid<bmfma_stage_kernel<N, STAGE, MAT, SRC>>(BDims<N>::THREADS, ntiles);
+  bmfma_stage_kernel<N, STAGE, MAT, SRC><<<nb, BDims<N>::THREADS, 0, s>>>(
+      static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
+      static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
+      static_cast<const uint16_t*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
+      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f, a.src);
+  return hipGetLastError();
+}
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+struct BmfmaLaunch {
+  static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
+    return launch_bmfma_v<N, STAGE, MAT, SRC>(o, a, s);
   }
 };
 
@@ -1341,6 +2044,49 @@ int opcat_words(int N) {
 
 bool mfma_order(int N) { return contraction_order(N); }
 
+bool dmfma_order(int N) { return N == 3; }
+
+bool bf16x3_order(int N) { return N >= 5 && N <= 7; }
+
+int bopcat_words(int N) {
+  switch (N) {
+    case 5: return BDims<5>::OPW;
+    case 6: return BDims<6>::OPW;
+    case 7: return BDims<7>::OPW;
+  }
+  return 0;
+}
+
+namespace {
+template <typename D>
+void bopfrag_source_t(int w, int* n, int* blk, int* col, int* part) {
+  // w = ((nt KB + b) 64 + lane) 16 + part 8 + j: column 16 nt + lane mod 16 of the operator,
+  // k = 32 b + 8 (lane / 16) + j of the concatenation [D_r | D_s | D_t | LIFT]
+  const int j = w % 8, pt = (w / 8) % 2, lane = (w / 16) % 64, tb = w / 1024;
+  const int b = tb % D::KB, nt = tb / D::KB;
+  *n = 16 * nt + lane % 16;
+  *part = pt;
+  const int k = 32 * b + 8 * (lane / 16) + j;
+  if (k < D::KV) {
+    *blk = k / D::NP8;
+    *col = k % D::NP8;
+    if (*col >= D::Np) *col = D::Np;   // padding node: outside the operator (zero)
+  } else {
+    *blk = 3;
+    *col = k - D::KV;                  // >= 4 Nfp in the padding: outside the operator (zero)
+  }
+}
+}  // namespace
+
+void bopfrag_source(int N, int w, int* n, int* blk, int* col, int* part) {
+  switch (N) {
+    case 5: return bopfrag_source_t<BDims<5>>(w, n, blk, col, part);
+    case 6: return bopfrag_source_t<BDims<6>>(w, n, blk, col, part);
+    case 7: return bopfrag_source_t<BDims<7>>(w, n, blk, col, part);
+  }
+  *n = *blk = *col = *part = -1;
+}
+
 int row_stride(int N, bool f64) {
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   return (!f64 && contraction_order(N)) ? (Np + 3) / 4 * 4 : Np;
@@ -1410,6 +2156,13 @@ void opfrag_source(int N, int w, int* n, int* blk, int* col) {
 
 hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
                         hipStream_t s) {
+  if (a.split_bf16) {
+    if (N == 5) return launch_variant<5, BmfmaLaunch>(stage, ops, a, s);
+    if (N == 6) return launch_variant<6, BmfmaLaunch>(stage, ops, a, s);
+    if (N == 7) return launch_variant<7, BmfmaLaunch>(stage, ops, a, s);
+    return hipErrorInvalidValue;
+  }
+  if (f64 && ops.opfrag && N == 3) return launch_variant<3, DmfmaLaunch>(stage, ops, a, s);
   if (!f64 && ops.opfrag) {
     if (N == 3) return launch_mfma_t<3>(stage, ops, a, s);
     if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);

@@ -26,6 +26,17 @@ struct OpsView {
 int opcat_words(int N);
 // Whether the FP32 MFMA stage kernel serves order N.
 bool mfma_order(int N);
+// Whether the FP64 MFMA stage kernel serves order N (it reads the operator table of the FP32
+// kernel of the same order, in FP64).
+bool dmfma_order(int N);
+// Whether the split-BF16 contraction kernel serves order N.
+bool bf16x3_order(int N);
+// 16-bit words of its operator table (high and low bf16 parts in lane order).
+int bopcat_words(int N);
+// Word w of that table holds part `part` (0 high, 1 low) of row n of operator block blk
+// (0, 1, 2 = Dr, Ds, Dt; 3 = LIFT) at column col; zero when n or col fall outside the operator
+// (n >= Np, col >= Np for a D block, col >= 4 Nfp for LIFT).
+void bopfrag_source(int N, int w, int* n, int* blk, int* col, int* part);
 // Words per (element, field) row of the internal field arrays, [K][6][S]: Np, rounded up to a
 // multiple of 4 for the FP32 contraction orders (the pad words are kept zero).
 int row_stride(int N, bool f64);
@@ -54,6 +65,7 @@ struct StageArgs {
   int K;
   double a, b, dt;   // stage coefficients (stage mode only)
   SrcArgs src;       // scattered-field form (src.rec == NULL: none)
+  bool split_bf16 = false;   // FP32 state, split-BF16 contraction (operator table in bf16)
 };
 
 // One RHS evaluation (stage == false) or one fused LSRK4 stage (stage == true).

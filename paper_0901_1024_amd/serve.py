@@ -40,6 +40,7 @@ class Request:
     t_start: Optional[float] = None
     t_done: Optional[float] = None
     result: Optional[np.ndarray] = None
+    error: Optional[str] = None       # set when the numeric monitor stopped the solve
 
     @property
     def latency(self) -> float:
@@ -54,6 +55,7 @@ class _Active:
     dt: float
     left: int
     event: Any = None
+    e0: Optional[float] = None        # energy at admission (numeric monitor)
 
 
 def _percentile(v, q):
@@ -61,25 +63,32 @@ def _percentile(v, q):
 
 
 def summary(done):
-    """Throughput and latency of completed requests."""
+    """Throughput and latency of completed requests (requests stopped by the numeric monitor
+    are counted apart)."""
+    failed = [r for r in done if r.error is not None]
+    done = [r for r in done if r.error is None]
     if not done:
-        return {"completed": 0}
+        return {"completed": 0, "failed": len(failed)}
     t_end = max(r.t_done for r in done)
     t_first = min(r.arrival for r in done)
     lat = [r.latency for r in done]
     return {"completed": len(done), "makespan_s": t_end - t_first,
             "solves_per_s": len(done) / (t_end - t_first) if t_end > t_first else float("nan"),
             "p50_latency_s": _percentile(lat, 50), "p99_latency_s": _percentile(lat, 99),
-            "mean_latency_s": float(np.mean(lat))}
+            "mean_latency_s": float(np.mean(lat)), "failed": len(failed)}
 
 
 class Server:
     """budget_bytes: device memory the admitted solves may hold together; slots: solves in
     flight at once; chunk_steps: steps issued per scheduling round (even, so a solve reuses its
-    captured two-step graph); keep_results: copy each final state to the host."""
+    captured two-step graph); keep_results: copy each final state to the host; checks: after
+    every chunk, a solve whose energy is not finite or has grown (more than check_tol relative
+    to its energy at admission) is stopped and reported with `error`, and its memory freed; the
+    other solves are not affected."""
 
     def __init__(self, budget_bytes: int, slots: int = 8, chunk_steps: int = 64, device: int = 0,
-                 keep_results: bool = False, setup_threads: int = 4, backend=None):
+                 keep_results: bool = False, setup_threads: int = 4, backend=None, checks: bool = False,
+                 check_tol: float = 1e-4):
         if chunk_steps < 2 or chunk_steps % 2:
             raise ValueError("chunk_steps must be even and >= 2")
         self.budget = int(budget_bytes)
@@ -89,6 +98,8 @@ class Server:
         self.keep = keep_results
         self.setup_threads = setup_threads
         self.backend = backend if backend is not None else _DeviceBackend(device)
+        self.checks = checks
+        self.check_tol = check_tol
 
     def run(self, requests, clock=time.perf_counter, idle_sleep=2e-4):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -123,6 +134,20 @@ class Server:
                 for a in list(active):
                     if a.event is not None and not self.backend.finished(a.event):
                         continue
+                    if self.checks:
+                        # the stream is idle here (its last chunk has finished)
+                        e = self.backend.energy(a.solver, a.stream)
+                        if a.e0 is None and np.isfinite(e):
+                            a.e0 = e
+                        if not np.isfinite(e) or e > a.e0 * (1.0 + self.check_tol):
+                            a.req.error = f"numeric monitor: energy {e!r} after {a.req.steps - a.left} steps"
+                            a.req.t_done = clock() - t0
+                            self.backend.release(a.solver)
+                            used -= a.req.footprint
+                            active.remove(a)
+                            done.append(a.req)
+                            progressed = True
+                            continue
                     if a.left > 0:
                         n = min(self.chunk, a.left)
                         a.event = self.backend.advance(a.solver, a.stream, a.dt, n)
@@ -174,6 +199,9 @@ class _DeviceBackend:
 
     def finished(self, event):
         return event.query()
+
+    def energy(self, solver, stream):
+        return solver.energy(stream=stream)
 
     def fetch(self, solver, stream):
         out = solver.get_fields(stream=stream)

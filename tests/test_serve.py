@@ -69,3 +69,33 @@ def test_oversized_request_is_refused_and_chunks_are_even():
         Server(budget_bytes=100, slots=2, backend=FakeBackend()).run(_requests([10], [0.0]))
     with pytest.raises(ValueError):
         Server(budget_bytes=10 ** 6, chunk_steps=3, backend=FakeBackend())
+
+
+class MonitoredBackend(FakeBackend):
+    """Energies per request: request 1 turns non-finite after its first chunk, request 2 grows."""
+
+    def __init__(self):
+        super().__init__()
+        self.calls = {}
+
+    def energy(self, solver, stream):
+        r = solver[0]
+        k = self.calls.get(r.rid, 0)
+        self.calls[r.rid] = k + 1
+        if r.rid == 1 and k >= 1:
+            return float("nan")
+        if r.rid == 2:
+            return 1.0 + 0.01 * k
+        return 1.0 - 1e-6 * k
+
+
+def test_numeric_monitor_stops_only_the_bad_requests():
+    be = MonitoredBackend()
+    reqs = _requests([10, 20, 30, 40], [0.0] * 4, steps=8)
+    done = Server(budget_bytes=10 ** 6, slots=4, chunk_steps=2, backend=be, checks=True).run(reqs)
+    by = {r.rid: r for r in done}
+    assert len(done) == 4
+    assert by[1].error and "nan" in by[1].error and by[2].error and by[0].error is None and by[3].error is None
+    assert be.in_flight == 0 and be.used == 0          # stopped solves released their memory
+    s = summary(done)
+    assert s["completed"] == 2 and s["failed"] == 2
