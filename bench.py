@@ -278,7 +278,8 @@ def run_serve(args, rates=(0.5, 1.0, 2.0)):
 
     budget = 64 * 2 ** 30
     fifo = lambda: Server(budget, slots=1, chunk_steps=args.serve_chunk)
-    served = lambda: Server(budget, slots=args.serve_slots, chunk_steps=args.serve_chunk)
+    served = lambda: Server(budget, slots=args.serve_slots, chunk_steps=args.serve_chunk,
+                            backfill=args.serve_backfill)
     base = summary(fifo().run(requests(0.0)))
     cap = base["solves_per_s"]
     print(f"capacity (FIFO, all queued): {cap:.3f} solves/s", file=sys.stderr, flush=True)
@@ -300,7 +301,8 @@ def run_serve(args, rates=(0.5, 1.0, 2.0)):
         "data": "synthetic",
         "config": {"workload": f"{len(specs)} cavity solves, K log-uniform in [2e3, 2e5] (total {sum(Ks)}), "
                                "N uniform in 3..6, steps uniform in [100, 2000], FP32, Poisson arrivals (seed 5)",
-                   "slots": args.serve_slots, "chunk_steps": args.serve_chunk, "budget_bytes": budget},
+                   "slots": args.serve_slots, "chunk_steps": args.serve_chunk, "budget_bytes": budget,
+                   "backfill": args.serve_backfill},
         "capacity_fifo_solves_per_s": cap,
         f"at_{rates[-1]:g}x_rate": {"served_p50_s": top["served"]["p50_latency_s"],
                                     "served_p99_s": top["served"]["p99_latency_s"],
@@ -410,6 +412,8 @@ def main():
     ap.add_argument("--solves-serve-requests", type=int, default=12)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-chunk", type=int, default=64)
+    ap.add_argument("--serve-backfill", action="store_true",
+                    help="oldest request first, then the arrived request of least work")
     ap.add_argument("--material", action="store_true",
                     help="heterogeneous medium (eps, mu log-uniform in [1, 4]) with absorbing z = 1 faces")
     ap.add_argument("--copy-calibration", action="store_true",

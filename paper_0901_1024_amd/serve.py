@@ -58,6 +58,12 @@ class _Active:
     e0: Optional[float] = None        # energy at admission (numeric monitor)
 
 
+def work(r):
+    """Work estimate of a request: steps x elements x Np^2 (the contraction dominates)."""
+    Np = (r.order + 1) * (r.order + 2) * (r.order + 3) // 6
+    return r.steps * r.etov.shape[0] * Np * Np
+
+
 def _percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else float("nan")
 
@@ -80,15 +86,18 @@ def summary(done):
 
 class Server:
     """budget_bytes: device memory the admitted solves may hold together; slots: solves in
-    flight at once; chunk_steps: steps issued per scheduling round (even, so a solve reuses its
+    flight at once (default 4, the hardware queues a process gets: more streams would share
+    queues and serialise); backfill: the first free slot takes the oldest waiting request, any
+    further one the arrived request of least work (so small solves run beside a large one
+    instead of queueing behind it); chunk_steps: steps issued per scheduling round (even, so a solve reuses its
     captured two-step graph); keep_results: copy each final state to the host; checks: after
     every chunk, a solve whose energy is not finite or has grown (more than check_tol relative
     to its energy at admission) is stopped and reported with `error`, and its memory freed; the
     other solves are not affected."""
 
-    def __init__(self, budget_bytes: int, slots: int = 8, chunk_steps: int = 64, device: int = 0,
+    def __init__(self, budget_bytes: int, slots: int = 4, chunk_steps: int = 64, device: int = 0,
                  keep_results: bool = False, setup_threads: int = 4, backend=None, checks: bool = False,
-                 check_tol: float = 1e-4):
+                 check_tol: float = 1e-4, backfill: bool = False):
         if chunk_steps < 2 or chunk_steps % 2:
             raise ValueError("chunk_steps must be even and >= 2")
         self.budget = int(budget_bytes)
@@ -100,6 +109,7 @@ class Server:
         self.backend = backend if backend is not None else _DeviceBackend(device)
         self.checks = checks
         self.check_tol = check_tol
+        self.backfill = backfill
 
     def run(self, requests, clock=time.perf_counter, idle_sleep=2e-4):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -114,11 +124,19 @@ class Server:
         with ThreadPoolExecutor(max_workers=self.setup_threads) as pool:
             while pending or setting_up or active:
                 now = clock() - t0
-                # admit in arrival order while a slot and memory are free
-                while (pending and pending[0].arrival <= now
-                       and len(setting_up) + len(active) < self.slots
-                       and used + pending[0].footprint <= self.budget):
-                    r = pending.pop(0)
+                # admit while a slot and memory are free: the oldest waiting request first;
+                # with the backfill policy a slot beyond the first goes to the arrived request
+                # of least work instead
+                while len(setting_up) + len(active) < self.slots:
+                    arrived = [r for r in pending if r.arrival <= now]
+                    if not arrived:
+                        break
+                    r = arrived[0]
+                    if self.backfill and (setting_up or active):
+                        r = min(arrived, key=work)
+                    if used + r.footprint > self.budget:
+                        break
+                    pending.remove(r)
                     used += r.footprint
                     r.t_admit = now
                     setting_up.append((r, pool.submit(self.backend.setup, r)))

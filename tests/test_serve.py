@@ -99,3 +99,16 @@ def test_numeric_monitor_stops_only_the_bad_requests():
     assert be.in_flight == 0 and be.used == 0          # stopped solves released their memory
     s = summary(done)
     assert s["completed"] == 2 and s["failed"] == 2
+
+
+def test_backfill_admits_oldest_first_then_smallest():
+    be = FakeBackend()
+    # request 0 arrives first; then a large one (1) and a small one (2)
+    reqs = _requests([50, 40, 5], [0.0, 0.0, 0.0], steps=4)
+    done = Server(budget_bytes=10 ** 6, slots=2, chunk_steps=2, backend=be, backfill=True).run(reqs)
+    by = {r.rid: r for r in done}
+    assert by[0].t_admit <= by[2].t_admit <= by[1].t_admit      # oldest, then least work
+    plain = Server(budget_bytes=10 ** 6, slots=2, chunk_steps=2, backend=FakeBackend()).run(
+        _requests([50, 40, 5], [0.0, 0.0, 0.0], steps=4))
+    pb = {r.rid: r for r in plain}
+    assert pb[1].t_admit <= pb[2].t_admit                        # arrival order without backfill
