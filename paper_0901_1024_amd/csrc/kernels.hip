@@ -1102,17 +1102,21 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 // Result layouts: 16x16x4, lane (li, g4) register i = row g4 + 4 i, column li; 4x4x4, lane
 // (li, g4) = row 4 (li / 4) + g4, column li mod 4.
 //
-// One wave per field: a tile of 16 elements has six 16-row tiles (field f, element li), and
-// wave f computes all column tiles and the tail of row tile f, so the six waves carry equal
-// matrix work. Fields, fluxes and the operator table sit in LDS; the next tile's fields,
-// geometry and exterior traces are loaded into registers during this tile, every load issued
-// on every path with clamped indices (as in the FP32 kernels).
+// One wave per 16-row tile: a tile of 8 elements has 48 (field, element) rows, field-major,
+// and wave t computes all column tiles and the tail of rows 16 t .. 16 t + 15, so the three
+// waves carry equal matrix work. Fields, fluxes and the operator table sit in LDS (47 KB: three
+// workgroups per CU; 16-element tiles with six waves and two workgroups per CU ran 16 %
+// slower); the next tile's fields, geometry and exterior traces are loaded into registers
+// during this tile, every load issued on every path with clamped indices (as in the FP32
+// kernels). Issue priorities as in the FP32 kernels (contraction 3, fluxes 2, memory phases 0).
+// The residual is read and the new state and residual written with nontemporal hints: each is
+// touched once per stage, so they need not displace the neighbour traces in L2.
 template <int N>
 struct DDims {
   using M = MDims<N>;                                 // operand and operator geometry
   static constexpr int Np = M::Np, Nfp = M::Nfp, Nf4 = M::Nf4;
-  static constexpr int E = 16;                        // elements per tile
-  static constexpr int WAVES = 6, THREADS = 64 * WAVES;
+  static constexpr int E = 8;                         // elements per tile
+  static constexpr int WAVES = 6 * E / 16, THREADS = 64 * WAVES;   // one wave per 16-row tile
   static constexpr int NPP = M::NPP;                  // row stride of the field arrays
   static constexpr int ES = 6 * NPP + 2;              // element stride in LDS (doubles, = 2 mod 4)
   static constexpr int NF = M::NF, RSL = NF + 2;      // flux row stride (doubles, = 2 mod 4)
@@ -1156,7 +1160,7 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   __shared__ uint8_t fm_s[4 * NFP];
 
   const int tid = threadIdx.x, lane = tid & 63;
-  const int fw = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's field (row tile)
+  const int fw = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's 16-row tile
   const int g4 = lane >> 4, li = lane & 15;
   auto slot = [](int q) __attribute__((always_inline)) {
     const int e = q / (6 * NPP);
@@ -1263,6 +1267,7 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 
     // ---- face fluxes from the exterior traces gathered during the previous tile
     const int32_t* fc = fcb[par];
+    __builtin_amdgcn_s_setprio(2);
     {
       if constexpr (NF > NF4)
         for (int q = tid; q < 6 * E * (NF - NF4); q += NTH) {
@@ -1293,34 +1298,38 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
       }
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     doublex2 rs[CPT];
     if (STAGE) {
 #pragma unroll
       for (int r = 0; r < CPT; ++r)
-        rs[r] = reinterpret_cast<const doublex2*>(res)[min(size_t(tile) * TC + min(tid + r * NTH, TC - 1), chunk_last)];
+        rs[r] = __builtin_nontemporal_load(reinterpret_cast<const doublex2*>(res) +
+                                           min(size_t(tile) * TC + min(tid + r * NTH, TC - 1), chunk_last));
     }
     // the next tile's fields and geometry, then its exterior traces
     prefetch(nxt);
     gather(nxt, fcb[more ? par ^ 1 : par]);
 
-    // ---- contraction of row tile fw (field fw, element li)
+    // ---- contraction of row tile fw: row 16 fw + li = (field f, element el)
+    __builtin_amdgcn_s_setprio(3);
     doublex4 acc[NT];
     double tacc = 0.0;
     {
-      const int a = fw % 3, b = (a + 1) % 3, c = (a + 2) % 3;
-      const int srcf = fw < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
-      const double sg = fw < 3 ? 1.0 : -1.0;
-      const double* cm = gt + li * G;
-      const double sm = MAT ? sg * up_s[li * ES + 6 * NPP + (fw < 3 ? 0 : 1)] : sg;
+      const int row = 16 * fw + li, f = row / E, el = row - f * E;
+      const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+      const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
+      const double sg = f < 3 ? 1.0 : -1.0;
+      const double* cm = gt + el * G;
+      const double sm = MAT ? sg * up_s[el * ES + 6 * NPP + (f < 3 ? 0 : 1)] : sg;
       double pc[3], qc[3];   // operand = pc[mu] V_c + qc[mu] V_b
 #pragma unroll
       for (int mu = 0; mu < 3; ++mu) {
         pc[mu] = sm * cm[3 * mu + b];
         qc[mu] = -sm * cm[3 * mu + c];
       }
-      const double* vc = up_s + li * ES + (srcf + c) * NPP;
-      const double* vb = up_s + li * ES + (srcf + b) * NPP;
-      const double* fl = gl + (fw * E + li) * RSL + 4 * g4;
+      const double* vc = up_s + el * ES + (srcf + c) * NPP;
+      const double* vb = up_s + el * ES + (srcf + b) * NPP;
+      const double* fl = gl + row * RSL + 4 * g4;
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
       auto ld4 = [](const double* p) __attribute__((always_inline)) {
@@ -1382,12 +1391,19 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
     __syncthreads();   // flux rows are read: reuse them for the staging
 
     // ---- stage the right-hand side [e][f][n] (laid out like up_s)
+    __builtin_amdgcn_s_setprio(0);
     double* stage = gl;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) stage[(g4 + 4 * i) * ES + fw * NPP + 16 * t + li] = acc[t][i];
-    if ((li & 3) < TAIL) stage[(4 * (li >> 2) + g4) * ES + fw * NPP + 16 * NT + (li & 3)] = tacc;
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * fw + g4 + 4 * i, f = row / E, el = row - f * E;
+        stage[el * ES + f * NPP + 16 * t + li] = acc[t][i];
+      }
+    if ((li & 3) < TAIL) {
+      const int row = 16 * fw + 4 * (li >> 2) + g4, f = row / E, el = row - f * E;
+      stage[el * ES + f * NPP + 16 * NT + (li & 3)] = tacc;
+    }
     __syncthreads();
 
     // ---- update and write out, 16-byte chunks
@@ -1403,8 +1419,8 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
           if (STAGE) {
             const doublex2 u = *reinterpret_cast<const doublex2*>(up_s + o);
             const doublex2 rv = doublex2{ca * rs[r].x + cdt * h.x, ca * rs[r].y + cdt * h.y};
-            r2[c] = rv;
-            o2[c] = doublex2{u.x + cb * rv.x, u.y + cb * rv.y};
+            __builtin_nontemporal_store(rv, r2 + c);
+            __builtin_nontemporal_store(doublex2{u.x + cb * rv.x, u.y + cb * rv.y}, o2 + c);
           } else {
             o2[c] = h;
           }

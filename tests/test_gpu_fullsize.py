@@ -85,8 +85,8 @@ def test_fp32_full_size_steady_state_loop(N, n, medium):
 
 @pytest.mark.parametrize("medium", [False, True])
 def test_fp64_contraction_kernel_full_size(medium):
-    """FP64 N = 3 on its contraction kernel at full size (16-element tiles, 355,914 = 16 *
-    22,244 + 10 elements: a ragged last tile), vacuum and medium with absorbing faces."""
+    """FP64 N = 3 on its contraction kernel at full size (8-element tiles, 355,914 = 8 *
+    44,489 + 2 elements: a ragged last tile), vacuum and medium with absorbing faces."""
     v, e, m, u, eps, mu, fb, absorb = big_problem(3, 39)
     say(f"case: N=3 K={m.K} f64 full size, shuffled vertices, {'medium+absorbing' if medium else 'vacuum'}")
     kw = dict(eps=eps, mu=mu, absorb=absorb) if medium else {}
