@@ -293,5 +293,5 @@ def stable_dt(mesh: Mesh, cfl=0.5):
 def l2_error(mesh: Mesh, u, uref):
     """Mass-weighted L2 norms over all six fields: (||u - uref||, ||uref||)."""
     def nrm(v):
-        return float(np.sqrt(np.einsum("fki,ij,fkj,k->", v, mesh.ref.M, v, mesh.J)))
+        return float(np.sqrt(np.einsum("fki,ij,fkj,k->", v, mesh.ref.M, v, mesh.J, optimize=True)))
     return nrm(u - uref), nrm(uref)
