@@ -203,6 +203,20 @@ def run_batch(args):
     grp = P.Group(list(batched.values()))
     t_batch = timed(lambda n: grp.solve(np.ones(len(batched)), n))
     timed(lambda n: [s.solve(dts[i], n) for i, s in enumerate(plain)])
+    # each order's graph on a stream of its own, joined on the timing stream
+    streams = [torch.cuda.Stream() for _ in batched]
+
+    def on_streams(n):
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        for st, b in zip(streams, batched.values()):
+            st.wait_event(ev)
+            b.solve(1.0, n, stream=st)
+        for st in streams:
+            stream.wait_stream(st)
+
+    t_streams = timed(on_streams)
+    timed(lambda n: [s.solve(dts[i], n) for i, s in enumerate(plain)])
     worst = 0.0
     for N, idx in groups.items():
         got = batched[N].get_fields()
@@ -228,7 +242,8 @@ def run_batch(args):
         "speedup_batched_over_plain": round(t_plain / t_batch, 3),
         "batched_gflops": round(flops / t_batch / 1e9, 1), "plain_gflops": round(flops / t_plain / 1e9, 1),
         "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4),
-                    "batched_one_graph_per_order": round(t_orders, 4)},
+                    "batched_one_graph_per_order": round(t_orders, 4),
+                    "batched_one_stream_per_order": round(t_streams, 4)},
         "max_rel_diff_batched_vs_plain": worst,
     }
     for s_ in plain:
@@ -494,6 +509,20 @@ def main():
         z.synchronize()
         reps.append(a.elapsed_time(z) * 1e3 / 10.0)
     reps_us = np.array(reps)
+    # the exported right-hand side (dg_rhs: canonical arrays in and out, two permutes around
+    # one stage kernel in right-hand-side mode), median of 10 calls
+    u_c = torch.empty(6 * K * Np, dtype=torch.float64 if prec == "f64" else torch.float32, device="cuda")
+    s.get_fields(out=u_c)
+    r_c = torch.empty_like(u_c)
+    rhs_us = []
+    for _ in range(10):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.rhs(u_c, r_c)
+        z.record(stream)
+        z.synchronize()
+        rhs_us.append(a.elapsed_time(z) * 1e3)
+    del u_c, r_c
     e1 = s.energy()
     print(f"timed {args.steps} steps: {ms:.3f} ms (wall {wall * 1e3:.1f} ms); energy {e0:.6e} -> {e1:.6e}",
           file=sys.stderr, flush=True)
@@ -519,7 +548,8 @@ def main():
                 "frac": round(tflops_k / PEAKS_TFLOPS[prec], 4)}
     roof["traffic"] = None if args.material else recorded_traffic(N, prec, K)
     mat = "true" if args.material else "false"
-    roof["kernel"] = (f"mfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (3, 4)
+    roof["kernel"] = (f"smfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N == 3
+                      else f"mfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N == 4
                       else f"hmfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (5, 6, 7)
                       else f"dmfma_stage_kernel<{N},true,{mat},false>" if prec == "f64" and N == 3
                       else f"bmfma_stage_kernel<{N},true,{mat},false>" if prec == "bf16x3"
@@ -528,6 +558,7 @@ def main():
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     roof["tflops_algorithmic"] = round(tflops_k, 2)
     roof["us_per_launch"] = round(per_launch_s * 1e6, 2)
+    roof["dg_rhs_us"] = round(float(np.median(rhs_us)), 2)
     if len(reps_us):
         roof["launch_us_reps"] = {"median": round(float(np.median(reps_us)), 2),
                                   "p10": round(float(np.percentile(reps_us, 10)), 2),

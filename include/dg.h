@@ -207,7 +207,10 @@ int dg_stable_dt(const dg_handle* h, double cfl, double* dt);
  * multiplies the per-mesh steps (pass 1.0). dg_rhs, dg_energy and the field calls see the
  * unscaled operator. Meshes may differ in K, geometry, face conditions and materials. */
 
-/* Workspace bytes for dg_setup_batch with the same arguments. */
+/* Workspace bytes for dg_setup_batch with the same arguments. A batch handle holds a second
+ * copy of the geometric records (and, in a medium, of the material records) scaled by each
+ * mesh's time step, so its metadata takes twice the bytes of a plain handle's (26 words per
+ * element, plus 20 in a medium, in the working precision). */
 int dg_setup_query_batch(const dg_mesh* meshes, int32_t count, const dg_opts* opts,
                          size_t* workspace_bytes);
 

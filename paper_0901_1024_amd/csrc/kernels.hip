@@ -1771,6 +1771,364 @@ __global__ __launch_bounds__(BDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// FP32 contraction on small tiles (serves N = 3): the structure of the FP64 kernel above with
+// the FP32 matrix instructions. A tile of 8 elements has 48 field-major (field, element) rows;
+// wave t computes row tile t (rows 16 t .. 16 t + 15) against all column tiles on
+// v_mfma_f32_16x16x4f32 and the Np mod 16 tail columns on v_mfma_f32_4x4x1f32 (its 16 blocks
+// read as (k-group, row quad) pairs from the same operand register, a cross-lane sum over the
+// k-groups at the end, as in the 16-element kernel), so the three waves carry equal matrix
+// work; LDS holds the fields, the fluxes and the operator (three workgroups per CU). The field
+// arrays keep their padded rows (roundup(Np, 4) words, pad words zero); the next tile's loads
+// are issued during the contraction; issue priorities; nontemporal residual and state I/O.
+// Measured on 384,000 tets: N = 3 212.3 us per stage against 259.0 us on the 16-element
+// kernel; at N = 4 it is slower (483 against 422 us), so N = 4 keeps the 16-element kernel.
+template <int N>
+struct SDims {
+  using M = MDims<N>;
+  static constexpr int Np = M::Np, Nfp = M::Nfp, Nf4 = M::Nf4;
+  static constexpr int E = 8;                         // elements per tile
+  static constexpr int WAVES = 6 * E / 16, THREADS = 64 * WAVES;
+  static constexpr int NPP = M::NPP;                  // padded row of the field arrays
+  static constexpr int ES = 6 * NPP + 4;              // element stride in LDS (= 4 mod 8 words)
+  static constexpr int NF = M::NF, RSL = NF + 4;      // flux row stride (= 4 mod 8 words)
+  static constexpr int KS = M::KS, VB = M::VB, VR = M::VR, QV = M::QV, QF = M::QF, NQ = M::NQ;
+  static constexpr int NT = M::NT, TAIL = M::TAIL;
+  static constexpr int PC = NPP / 4;                  // 16-byte chunks per padded row
+  static constexpr int LAST = Np - 4 * (PC - 1);      // field words in the last chunk of a row
+  static constexpr int TW = E * 6 * NPP;
+  static constexpr int TC = TW / 4;                   // 16-byte chunks per tile
+  static constexpr int CPT = (TC + THREADS - 1) / THREADS;
+  static constexpr int FIT = (E * Nf4 + THREADS - 1) / THREADS;
+  static constexpr int OPC = M::OPC;
+  static_assert(TAIL > 0 && TAIL <= 4, "one 4-column tail block");
+  static_assert(E * ES <= 6 * E * RSL, "staging fits in the flux rows");
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+__global__ __launch_bounds__(SDims<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void smfma_stage_kernel(
+    const float* __restrict__ u_in, float* __restrict__ out, float* __restrict__ res,
+    const float* __restrict__ geo, const int32_t* __restrict__ fcode, const float* __restrict__ mat,
+    const float* __restrict__ opf, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, float ca, float cb, float cdt, SrcArgs inc) {
+  using D = SDims<N>;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES, NF = D::NF,
+                KS = D::KS, RSL = D::RSL, NT = D::NT, TAIL = D::TAIL, FIT = D::FIT, TC = D::TC, CPT = D::CPT,
+                VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF, NQ = D::NQ, NTH = D::THREADS, PC = D::PC,
+                LAST = D::LAST;
+  constexpr int G = dgh::kGeoStride;
+  constexpr int GW = E * G;
+  constexpr int GPT = (GW + NTH - 1) / NTH;
+  __shared__ __align__(16) float up_s[E * ES];             // field tile [e][f][NPP]
+  __shared__ __align__(16) float gl[6 * E * RSL];          // flux rows [f E + e][fj]; later staging
+  __shared__ __align__(16) float bfs[NT * KS * 64];        // operator fragments
+  __shared__ __align__(16) float tops[KS * 16];            // tail operator (k-group, column)
+  __shared__ float gt[GW];
+  __shared__ __align__(16) float wmat[MAT ? E * 4 * dgh::kMatFace : 4];   // MAT: [e][f][A B C D]
+  __shared__ int32_t fcb[2][E * 4];
+  __shared__ uint8_t nbr_s[96 * NFP];
+  __shared__ uint8_t fm_s[4 * NFP];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int fw = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's 16-row tile
+  const int g4 = lane >> 4, li = lane & 15;
+  auto slot = [](int q) __attribute__((always_inline)) {
+    const int e = q / (6 * NPP);
+    return e * ES + (q - e * 6 * NPP);
+  };
+  auto pad_zero = [](int c, floatx4 v) __attribute__((always_inline)) {   // pad words of a row
+    if (LAST < 4 && c % PC == PC - 1) {
+      if (LAST <= 3) v.w = 0.f;
+      if (LAST <= 2) v.z = 0.f;
+      if (LAST <= 1) v.y = 0.f;
+    }
+    return v;
+  };
+
+  const int nwg = gridDim.x / kXcds;
+  const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
+  const int TX = (ntiles + kXcds - 1) / kXcds;
+  const int tend = min(ntiles, (xcd + 1) * TX);
+  int tile = xcd * TX + wj;
+  if (tile >= tend) return;
+
+  for (int q = tid; q < NT * KS * 64; q += NTH) bfs[q] = opf[q];
+  for (int q = tid; q < KS * 16; q += NTH) tops[q] = opf[NT * KS * 64 + q];
+  for (int q = tid; q < 96 * NFP; q += NTH) nbr_s[q] = uint8_t(nbrnode[q]);
+  for (int q = tid; q < 4 * NFP; q += NTH) fm_s[q] = uint8_t(fmask[q]);
+  for (int q = tid; q < E * ES; q += NTH) up_s[q] = 0.f;
+  __syncthreads();
+
+  int tq = tid;
+  if (MAT) asm volatile("" : "+v"(tq));
+  floatx4 pu[CPT];
+  float pg[GPT];
+  float nup[FIT][6];
+  int32_t pf = 0;
+  float pm = 0.f, pw = 0.f;
+  const size_t fc_last = size_t(K) * 4 - 1;
+  const size_t chunk_last = size_t(K) * 6 * NPP / 4 - 1;
+  const floatx4* u4 = reinterpret_cast<const floatx4*>(u_in);
+  auto prefetch = [&](int t) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) pu[r] = u4[min(size_t(t) * TC + min(tid + r * NTH, TC - 1), chunk_last)];
+#pragma unroll
+    for (int r = 0; r < GPT; ++r)
+      pg[r] = geo[min(size_t(t) * GW + min(tid + r * NTH, GW - 1), size_t(K) * G - 1)];
+    if (MAT) {
+      const int q = min(tid, 2 * E - 1);
+      const size_t e = min(size_t(t) * E + q / 2, size_t(K) - 1);
+      pm = mat[e * dgh::kMatStride + (q & 1)];
+      const int qw = min(tid, 16 * E - 1);
+      const size_t ew = min(size_t(t) * E + qw / 16, size_t(K) - 1);
+      pw = mat[ew * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
+    }
+    pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+  };
+  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+    const int e0 = t * E, nl = min(E, K - e0);
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = min(tq + r * NTH, nl * NF4 - 1);
+      const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+      const int code = fcv[e * 4 + f];
+      const int ci = code >= 0 ? code : 0;
+      const int nn = nbr_s[((f * 4 + (ci & 3)) * 6 + ((ci >> 2) & 7)) * NFP + j];
+      const float* p = u_in + (code >= 0 ? size_t(ci >> 5) * 6 * NPP + nn : size_t(e0 + e) * 6 * NPP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nup[r][c] = p[c * NPP];
+    }
+  };
+  int par = 0;
+  if (tid < E * 4) {
+    fcb[0][tid] = fcode[min(size_t(tile) * E * 4 + tid, fc_last)];
+    fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
+  }
+  __syncthreads();
+  gather(tile, fcb[0]);
+  prefetch(tile);
+  pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+
+  for (; tile < tend; tile += nwg) {
+    const int base = tile * E;
+    const int nel = min(E, K - base);
+    const bool full = nel == E;
+    const size_t tb = size_t(base) * 6 * NPP;
+    const bool more = tile + nwg < tend;
+    const int nxt = more ? tile + nwg : tile;
+
+    // ---- tile into LDS
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if ((r + 1) * NTH <= TC || c < TC) *reinterpret_cast<floatx4*>(up_s + slot(4 * c)) = pu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < GW) gt[q] = pg[r];
+      }
+      if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * E) wmat[tid] = pw;
+    } else {
+      for (int q = tid; q < nel * 6 * NPP; q += NTH) up_s[slot(q)] = u_in[tb + q];
+      if (MAT) {
+        for (int q = tid; q < 2 * nel; q += NTH)
+          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+        for (int q = tid; q < 16 * nel; q += NTH)
+          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      }
+      for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
+    }
+    __syncthreads();
+
+    // ---- face fluxes from the exterior traces gathered during the previous tile
+    const int32_t* fc = fcb[par];
+    __builtin_amdgcn_s_setprio(2);
+    {
+      if constexpr (NF > NF4)
+        for (int q = tid; q < 6 * E * (NF - NF4); q += NTH) {
+          const int row = q / (NF - NF4);
+          gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.f;
+        }
+#pragma unroll
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tq + r * NTH;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          const float* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+          const float nx = g[0], ny = g[1], nz = g[2], hs = 0.5f * g[3];
+          const float* um = up_s + e * ES + fm_s[f * NFP + j];
+          float m[6], d[6], w[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < 6; ++c) m[c] = um[c * NPP];
+          const int code = fc[e * 4 + f];
+          if (SRC && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
+          face_jump(code, m, nup[r], d);
+          if (MAT) {
+            const floatx4 wv = *reinterpret_cast<const floatx4*>(wmat + 16 * e + 4 * f);
+            w[0] = wv.x, w[1] = wv.y, w[2] = wv.z, w[3] = wv.w;
+          }
+          upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
+        }
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
+    floatx4 rs[CPT];
+    if (STAGE) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r)
+        rs[r] = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(res) +
+                                           min(size_t(tile) * TC + min(tid + r * NTH, TC - 1), chunk_last));
+    }
+    // the next tile's fields and geometry, then its exterior traces
+    prefetch(nxt);
+    gather(nxt, fcb[more ? par ^ 1 : par]);
+
+    // ---- contraction of row tile fw: row 16 fw + li = (field f, element el)
+    __builtin_amdgcn_s_setprio(3);
+    floatx4 acc[NT], tacc = floatx4{0.f, 0.f, 0.f, 0.f};
+    {
+      const int row = 16 * fw + li, f = row / E, el = row - f * E;
+      const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+      const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
+      const float sg = f < 3 ? 1.f : -1.f;
+      const float* cm = gt + el * G;
+      const float sm = MAT ? sg * up_s[el * ES + 6 * NPP + (f < 3 ? 0 : 1)] : sg;
+      float pc[3], qc[3];   // operand = pc[mu] V_c + qc[mu] V_b
+#pragma unroll
+      for (int mu = 0; mu < 3; ++mu) {
+        pc[mu] = sm * cm[3 * mu + b];
+        qc[mu] = -sm * cm[3 * mu + c];
+      }
+      const float* vc = up_s + el * ES + (srcf + c) * NPP;
+      const float* vb = up_s + el * ES + (srcf + b) * NPP;
+      const float* fl = gl + row * RSL + 4 * g4;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const floatx4* bq = reinterpret_cast<const floatx4*>(bfs) + lane;   // quad q of tile t: bq[(t KS + 4 q) 16]
+      const float* bs = bfs + NQ * 256 + lane;                             // single s of tile t: bs[t KS 64 + 64 s]
+      const int tl = 4 * g4 + (li & 3);
+      const floatx4* tq4 = reinterpret_cast<const floatx4*>(tops) + tl;   // tail quad q: tq4[16 q]
+      const float* ts1 = tops + NQ * 64 + tl;                              // tail single s: ts1[16 s]
+      auto step = [&](float av, const floatx4 (&w)[NT], const floatx4& z, int s) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w[t][s], acc[t], 0, 0, 0);
+        tacc = __builtin_amdgcn_mfma_f32_4x4x1f32(av, z[s], tacc, 0, 0, 0);
+      };
+#pragma unroll
+      for (int jb = 0; jb < VB; ++jb) {
+        const floatx4 xc = *reinterpret_cast<const floatx4*>(vc + 16 * jb + 4 * g4);
+        const floatx4 xb = *reinterpret_cast<const floatx4*>(vb + 16 * jb + 4 * g4);
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const int q = 3 * jb + mu;
+          floatx4 w[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) w[t] = bq[(t * KS) * 16 + 64 * q];
+          const floatx4 z = tq4[16 * q];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) step(pc[mu] * xc[s] + qc[mu] * xb[s], w, z, s);
+        }
+      }
+#pragma unroll
+      for (int fb = 0; fb < QF; ++fb) {
+        const int q = QV + fb;
+        const floatx4 xf = *reinterpret_cast<const floatx4*>(fl + 16 * fb);
+        floatx4 w[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t] = bq[(t * KS) * 16 + 64 * q];
+        const floatx4 z = tq4[16 * q];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) step(xf[s], w, z, s);
+      }
+#pragma unroll
+      for (int r = 0; r < VR; ++r) {
+        const float xc1 = vc[16 * VB + 4 * r + g4];   // columns >= Np read the zero padding
+        const float xb1 = vb[16 * VB + 4 * r + g4];
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const int sgl = 3 * r + mu;
+          const float av = pc[mu] * xc1 + qc[mu] * xb1;
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bs[t * KS * 64 + 64 * sgl], acc[t], 0, 0, 0);
+          tacc = __builtin_amdgcn_mfma_f32_4x4x1f32(av, ts1[16 * sgl], tacc, 0, 0, 0);
+        }
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    // tail: sum the partial results of the four k-groups (lanes li, li + 16, li + 32, li + 48)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = tacc[i];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      tacc[i] = v;
+    }
+    __syncthreads();   // flux rows are read: reuse them for the staging
+
+    // ---- stage the right-hand side [e][f][NPP] (laid out like up_s). 16x16x4 result: lane
+    // (li, g4), register i = row 16 fw + 4 g4 + i, node 16 t + li. Tail (lanes g4 = 0): lane li,
+    // register i = row 16 fw + 4 (li / 4) + i, node 16 NT + li mod 4.
+    float* stage = gl;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * fw + 4 * g4 + i, f = row / E, el = row - f * E;
+        stage[el * ES + f * NPP + 16 * t + li] = acc[t][i];
+      }
+    if (g4 == 0 && (li & 3) < TAIL) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * fw + 4 * (li >> 2) + i, f = row / E, el = row - f * E;
+        stage[el * ES + f * NPP + 16 * NT + (li & 3)] = tacc[i];
+      }
+    }
+    __syncthreads();
+
+    // ---- update and write out, 16-byte chunks (pad words written as zero)
+    if (full) {
+      floatx4* o4 = reinterpret_cast<floatx4*>(out + tb);
+      floatx4* r4 = reinterpret_cast<floatx4*>(res + tb);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if ((r + 1) * NTH <= TC || c < TC) {
+          const int o = slot(4 * c);
+          const floatx4 h = *reinterpret_cast<const floatx4*>(stage + o);
+          if (STAGE) {
+            const floatx4 u = *reinterpret_cast<const floatx4*>(up_s + o);
+            const floatx4 rv = pad_zero(c, ca * rs[r] + cdt * h);
+            __builtin_nontemporal_store(rv, r4 + c);
+            __builtin_nontemporal_store(u + cb * rv, o4 + c);
+          } else {
+            o4[c] = pad_zero(c, h);
+          }
+        }
+      }
+    } else {
+      for (int q = tid; q < nel * 6 * NPP; q += NTH) {
+        const bool node = q % NPP < NP;   // pad words stay zero
+        const float h = node ? stage[slot(q)] : 0.f;
+        if (STAGE) {
+          const float rv = node ? ca * res[tb + q] + cdt * h : 0.f;
+          res[tb + q] = rv;
+          out[tb + q] = up_s[slot(q)] + cb * rv;
+        } else {
+          out[tb + q] = h;
+        }
+      }
+    }
+    if (tile + 2 * nwg < tend && tid < E * 4) fcb[par][tid] = pf;
+    par ^= 1;
+    __syncthreads();   // the next tile overwrites up_s, gt, fcb and gl
+  }
+}
+
 // Resident workgroups for the persistent grid: CUs x workgroups per CU, a multiple of the XCD
 // count (queried once per kernel and device: the template argument is the kernel itself, so
 // every kernel keeps its own count).
@@ -1883,6 +2241,26 @@ template <int N, bool STAGE, bool MAT, bool SRC>
 struct BmfmaLaunch {
   static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
     return launch_bmfma_v<N, STAGE, MAT, SRC>(o, a, s);
+  }
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+hipError_t launch_smfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const int E = SDims<N>::E;
+  const int ntiles = (a.K + E - 1) / E;
+  const int nb = persistent_grid<smfma_stage_kernel<N, STAGE, MAT, SRC>>(SDims<N>::THREADS, ntiles);
+  smfma_stage_kernel<N, STAGE, MAT, SRC><<<nb, SDims<N>::THREADS, 0, s>>>(
+      static_cast<const float*>(a.u_in), static_cast<float*>(a.out), static_cast<float*>(a.res),
+      static_cast<const float*>(a.geo), a.fcode, static_cast<const float*>(a.mat),
+      static_cast<const float*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
+      STAGE ? float(a.a) : 0.f, STAGE ? float(a.b) : 0.f, STAGE ? float(a.dt) : 0.f, a.src);
+  return hipGetLastError();
+}
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+struct SmfmaLaunch {
+  static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
+    return launch_smfma_v<N, STAGE, MAT, SRC>(o, a, s);
   }
 };
 
@@ -2185,7 +2563,7 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
   }
   if (f64 && ops.opfrag && N == 3) return launch_variant<3, DmfmaLaunch>(stage, ops, a, s);
   if (!f64 && ops.opfrag) {
-    if (N == 3) return launch_mfma_t<3>(stage, ops, a, s);
+    if (N == 3) return launch_variant<3, SmfmaLaunch>(stage, ops, a, s);
     if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);
     if (N == 5) return launch_hmfma_t<5>(stage, ops, a, s);
     if (N == 6) return launch_hmfma_t<6>(stage, ops, a, s);

@@ -64,9 +64,9 @@ def check_sampled(s, m, u, kw, prec, nsample, nstep, seed):
     assert err1 <= TOL[prec] and mx1 <= MAX_TOL[prec]
 
 
-# (order, cube size n): K = 6 n^3 leaves a ragged last tile (16-element tiles at N = 3, 4:
-# 355,914 = 16 * 22,244 + 10; 8-element tiles at N = 5, 6: 178,746 = 8 * 22,343 + 2), and
-# every workgroup of the persistent grid takes many tiles
+# (order, cube size n): K = 6 n^3 leaves a ragged last tile (16-element tiles at N = 4:
+# 355,914 = 16 * 22,244 + 10; 8-element tiles at N = 3, 5, 6: 355,914 = 8 * 44,489 + 2 and
+# 178,746 = 8 * 22,343 + 2), and every workgroup of the persistent grid takes many tiles
 FULL = [(3, 39), (4, 39), (5, 31), (6, 31)]
 
 
@@ -99,8 +99,9 @@ def test_fp64_contraction_kernel_full_size(medium):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_all_face_orientations(N, prec):
     """Every (face, neighbour face, rotation) combination a conforming mesh allows, on every
-    kernel: FP64 at all orders; FP32 on the contraction kernels (N = 3..6) and the element-wise
-    kernel (N = 1, 2, 7). Whole-mesh right-hand side and one RK step."""
+    kernel: FP64 at all orders (the contraction kernel at N = 3); FP32 on the contraction
+    kernels (N = 3..7) and the element-wise kernel (N = 1, 2). Whole-mesh right-hand side and
+    one RK step."""
     v, e = dginputs.kuhn_cube(3, jitter=0.15, permute=True, shuffle=True)
     assert len(face_combos(v, e)) == 48
     m = Mm.Mesh(v, e, R.ref_element(N))

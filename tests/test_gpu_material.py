@@ -50,8 +50,8 @@ def test_medium_absorbing_fp64_all_orders(N):
 
 @pytest.mark.parametrize("N,n", [(2, 3), (3, 3), (3, 4), (4, 3), (4, 4), (6, 2)])
 def test_medium_absorbing_fp32(N, n):
-    """N = 3, 4 run on the 16-element contraction kernel (K = 162 ragged, 384 full tiles), N = 6
-    on the 8-element one, N = 2 on the element-wise kernel; the steady-state loops of the
+    """N = 4 runs on the 16-element contraction kernel (K = 162 ragged, 384 full tiles), N = 3
+    and N = 6 on 8-element ones, N = 2 on the element-wise kernel; the steady-state loops of the
     contraction kernels at full size are in test_gpu_fullsize.py."""
     say(f"case: medium+absorbing N={N} K={6 * n ** 3} f32")
     v, e, m, u0, eps, mu, fb, absorb = medium_problem(N, n)

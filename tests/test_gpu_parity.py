@@ -66,8 +66,8 @@ def test_all_orders_fp64_jittered_permuted(N):
 
 @pytest.mark.parametrize("N,n", [(2, 3), (3, 3), (4, 3), (4, 4), (5, 3), (5, 4), (6, 3), (6, 4), (7, 2)])
 def test_fp32_orders_small_mesh(N, n):
-    """K = 162 leaves a ragged last tile of every tile size; K = 384 fills them. N = 3, 4 run
-    on the 16-element MFMA kernel, N = 5, 6 on the 8-element one, N = 2, 7 on the VALU one."""
+    """K = 162 leaves a ragged last tile of every tile size; K = 384 fills them. N = 4 runs on
+    the 16-element MFMA kernel, N = 3, 5, 6, 7 on 8-element ones, N = 2 on the VALU one."""
     say(f"case: N={N} K={6 * n ** 3} f32 jitter+permute")
     v, e, m, u0 = problem(N, n, jitter=0.15, permute=True)
     s = P.Solver(v, e, N, "f32", reorder=1)
