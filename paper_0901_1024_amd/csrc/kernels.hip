@@ -1449,6 +1449,369 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 }
 
 // ---------------------------------------------------------------------------------------
+// MFMA form of the fused stage in FP64 at the high orders (N = 5, 6, 7).
+//
+// The contraction of the FP32 kernel for these orders (8-element tiles, three 16-row tiles
+// owned by every wave, one wave per 16-node column tile, the last one padded; the operator
+// table in the same fragment order, in FP64) on v_mfma_f64_16x16x4f64. In FP64 a wave's
+// operator strip is 2 KD VGPRs per lane (264 at N = 7), too large to keep resident, and the
+// whole operator (100-480 KB) does not fit in LDS beside the tile, so each wave streams its
+// strip from L2 (the table is a few hundred KB and every workgroup of an XCD reads it) with
+// LA quads in flight; each quad feeds RT x 4 matrix steps, which bounds the L2 traffic at
+// 8 / (4 RT) bytes per lane and multiply. The first quads are issued before the next tile's
+// prefetch, so their waits do not include those HBM loads. Exterior traces of the next tile
+// are gathered after the contraction (their registers are not live across it); the residual
+// is loaded after them, for the update. Issue priorities and nontemporal residual and state
+// I/O as in the other contraction kernels. Result layout: lane (li, g4) register i = row
+// 16 t + g4 + 4 i of row tile t, node 16 nt + li.
+template <int N>
+struct WDims {
+  using H = HDims<N>;                                 // tile, wave and operator geometry
+  static constexpr int Np = H::Np, Nfp = H::Nfp, Nf4 = H::Nf4, E = H::E, ROWS = H::ROWS;
+  static constexpr int RT = H::RT, NT = H::NT, THREADS = H::THREADS, NPP = H::NPP, NF = H::NF;
+  static constexpr int KS = H::KS, VB = H::VB, VR = H::VR, QV = H::QV, QF = H::QF, NQ = H::NQ;
+  static constexpr int FIT = H::FIT, OPC = H::OPC;
+  static constexpr int ES = 6 * NPP + 2;              // element stride in LDS (doubles, = 2 mod 4)
+  static constexpr int RSL = NF + 2;                  // flux row stride (doubles, = 2 mod 4)
+  static constexpr int TW = E * 6 * Np;               // doubles per tile
+  static constexpr int TC = TW / 2;                   // 16-byte chunks per tile
+  static constexpr int CPT = (TC + THREADS - 1) / THREADS;
+  static constexpr int LA = 3;                        // operator quads in flight per wave
+  static_assert(NPP == Np, "FP64 rows are unpadded");
+  static_assert(TW <= ROWS * RSL, "staging fits in the flux rows");
+  static_assert(NQ > LA, "the lookahead is shorter than the quad sequence");
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+__global__ __launch_bounds__(WDims<N>::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void wmfma_stage_kernel(
+    const double* __restrict__ u_in, double* __restrict__ out, double* __restrict__ res,
+    const double* __restrict__ geo, const int32_t* __restrict__ fcode, const double* __restrict__ mat,
+    const double* __restrict__ opf, const int32_t* __restrict__ fmask,
+    const int32_t* __restrict__ nbrnode, int K, int ntiles, double ca, double cb, double cdt, SrcArgs inc) {
+  using D = WDims<N>;
+  constexpr int NP = D::Np, NFP = D::Nfp, NF4 = D::Nf4, E = D::E, NPP = D::NPP, ES = D::ES, NF = D::NF,
+                KS = D::KS, RSL = D::RSL, RT = D::RT, FIT = D::FIT, TC = D::TC, CPT = D::CPT,
+                VB = D::VB, VR = D::VR, QV = D::QV, QF = D::QF, NQ = D::NQ, NTH = D::THREADS, LA = D::LA;
+  constexpr int G = dgh::kGeoStride;
+  constexpr int GW = E * G;
+  constexpr int GPT = (GW + NTH - 1) / NTH;
+  __shared__ __align__(16) double up_s[E * ES];            // field tile [e][f][n]
+  __shared__ __align__(16) double gl[D::ROWS * RSL];       // flux rows [f E + e][fj]; later staging
+  __shared__ double gt[GW];
+  __shared__ __align__(16) double wmat[MAT ? E * 4 * dgh::kMatFace : 2];   // MAT: [e][f][A B C D]
+  __shared__ int32_t fcb[2][E * 4];
+  __shared__ uint8_t nbr_s[96 * NFP];
+  __shared__ uint8_t fm_s[4 * NFP];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's column tile
+  const int g4 = lane >> 4, li = lane & 15;
+  auto slot = [](int q) __attribute__((always_inline)) {
+    const int e = q / (6 * NP);
+    return e * ES + (q - e * 6 * NP);
+  };
+
+  const int nwg = gridDim.x / kXcds;
+  const int xcd = blockIdx.x % kXcds, wj = blockIdx.x / kXcds;
+  const int TX = (ntiles + kXcds - 1) / kXcds;
+  const int tend = min(ntiles, (xcd + 1) * TX);
+  int tile = xcd * TX + wj;
+  if (tile >= tend) return;
+
+  for (int q = tid; q < 96 * NFP; q += NTH) nbr_s[q] = uint8_t(nbrnode[q]);
+  for (int q = tid; q < 4 * NFP; q += NTH) fm_s[q] = uint8_t(fmask[q]);
+  for (int q = tid; q < E * ES; q += NTH) up_s[q] = 0.0;
+  __syncthreads();
+
+  int tq = tid;
+  asm volatile("" : "+v"(tq));
+  doublex2 pu[CPT];
+  double pg[GPT];
+  double nup[FIT][6];
+  int32_t pf = 0;
+  double pm = 0.0, pw = 0.0;
+  const size_t fc_last = size_t(K) * 4 - 1;
+  const size_t chunk_last = size_t(K) * 6 * NP / 2 - 1;
+  const doublex2* u2 = reinterpret_cast<const doublex2*>(u_in);
+  // every load issued on every path, indices clamped into the arrays
+  auto prefetch = [&](int t) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) pu[r] = u2[min(size_t(t) * TC + min(tid + r * NTH, TC - 1), chunk_last)];
+#pragma unroll
+    for (int r = 0; r < GPT; ++r)
+      pg[r] = geo[min(size_t(t) * GW + min(tid + r * NTH, GW - 1), size_t(K) * G - 1)];
+    if (MAT) {
+      const int q = min(tid, 2 * E - 1);
+      const size_t e = min(size_t(t) * E + q / 2, size_t(K) - 1);
+      pm = mat[e * dgh::kMatStride + (q & 1)];
+      const int qw = min(tid, 16 * E - 1);
+      const size_t ew = min(size_t(t) * E + qw / 16, size_t(K) - 1);
+      pw = mat[ew * dgh::kMatStride + dgh::kMatFace + (qw & 15)];
+    }
+    pf = fcode[min(size_t(t + nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+  };
+  auto gather = [&](int t, const int32_t* fcv) __attribute__((always_inline)) {
+    const int e0 = t * E, nl = min(E, K - e0);
+#pragma unroll
+    for (int r = 0; r < FIT; ++r) {
+      const int q = min(tq + r * NTH, nl * NF4 - 1);
+      const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+      const int code = fcv[e * 4 + f];
+      const int ci = code >= 0 ? code : 0;
+      const int nn = nbr_s[((f * 4 + (ci & 3)) * 6 + ((ci >> 2) & 7)) * NFP + j];
+      const double* p = u_in + (code >= 0 ? size_t(ci >> 5) * 6 * NP + nn : size_t(e0 + e) * 6 * NP);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nup[r][c] = p[c * NP];
+    }
+  };
+  int par = 0;
+  if (tid < E * 4) {
+    fcb[0][tid] = fcode[min(size_t(tile) * E * 4 + tid, fc_last)];
+    fcb[1][tid] = fcode[min(size_t(tile + nwg) * E * 4 + tid, fc_last)];
+  }
+  __syncthreads();
+  gather(tile, fcb[0]);
+  prefetch(tile);
+  pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+
+  for (; tile < tend; tile += nwg) {
+    const int base = tile * E;
+    const int nel = min(E, K - base);
+    const bool full = nel == E;
+    const size_t tb = size_t(base) * 6 * NP;
+    const bool more = tile + nwg < tend;
+    const int nxt = more ? tile + nwg : tile;
+
+    // ---- tile into LDS
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if ((r + 1) * NTH <= TC || c < TC) *reinterpret_cast<doublex2*>(up_s + slot(2 * c)) = pu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < GW) gt[q] = pg[r];
+      }
+      if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * E) wmat[tid] = pw;
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += NTH) up_s[slot(q)] = u_in[tb + q];
+      if (MAT) {
+        for (int q = tid; q < 2 * nel; q += NTH)
+          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
+        for (int q = tid; q < 16 * nel; q += NTH)
+          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      }
+      for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
+    }
+    __syncthreads();
+
+    // ---- face fluxes from the exterior traces gathered during the previous tile
+    const int32_t* fc = fcb[par];
+    __builtin_amdgcn_s_setprio(2);
+    {
+      if constexpr (NF > NF4)
+        for (int q = tid; q < D::ROWS * (NF - NF4); q += NTH) {
+          const int row = q / (NF - NF4);
+          gl[row * RSL + NF4 + (q - row * (NF - NF4))] = 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < FIT; ++r) {
+        const int q = tq + r * NTH;
+        if (q < nel * NF4) {
+          const int e = q / NF4, fj = q - e * NF4, f = fj / NFP, j = fj - f * NFP;
+          const double* g = gt + e * G + dgh::kGeoNormal + 4 * f;
+          const double nx = g[0], ny = g[1], nz = g[2], hs = 0.5 * g[3];
+          const double* um = up_s + e * ES + fm_s[f * NFP + j];
+          double m[6], d[6], w[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int c = 0; c < 6; ++c) m[c] = um[c * NPP];
+          const int code = fc[e * 4 + f];
+          if (SRC && code <= dgh::kFaceScatter0) add_incident(inc, code, j, NFP, m);
+          face_jump(code, m, nup[r], d);
+          if (MAT) {
+            const doublex2 w01 = *reinterpret_cast<const doublex2*>(wmat + 16 * e + 4 * f);
+            const doublex2 w23 = *reinterpret_cast<const doublex2*>(wmat + 16 * e + 4 * f + 2);
+            w[0] = w01.x, w[1] = w01.y, w[2] = w23.x, w[3] = w23.y;
+          }
+          upwind_flux(MAT, nx, ny, nz, hs, w, d, gl + e * RSL + fj, E * RSL);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- contraction: this wave's column tile against the three row tiles; row tile t holds
+    // rows 16 t + li, row = f E + e
+    __builtin_amdgcn_s_setprio(3);
+    // this wave's operator strip: quad q at bq[64 q] (four k-steps), single s at bs[64 s]; the
+    // base address passes through an empty asm each tile, so the loads are not hoisted out of
+    // the tile loop (the whole strip would then have to stay resident)
+    const double* opw = opf + size_t(nt) * KS * 64;
+    asm volatile("" : "+s"(opw));
+    const doublex4* bq = reinterpret_cast<const doublex4*>(opw) + lane;
+    const double* bs = opw + NQ * 256 + lane;
+    doublex4 wb[LA];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) wb[i] = bq[64 * i];
+    double w1[3 * VR > 0 ? 3 * VR : 1];
+#pragma unroll
+    for (int i = 0; i < 3 * VR; ++i) w1[i] = bs[64 * i];
+    // the next tile's fields and geometry, issued behind the first operator quads
+    prefetch(nxt);
+    doublex4 acc[RT];
+    {
+      double pc[RT][3], qc[RT][3];   // operand = pc[mu] V_c + qc[mu] V_b
+      const double* vc[RT];
+      const double* vb[RT];
+      const double* fl[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+        const int row = 16 * t + li;
+        const int f = row / E, e = row - f * E;
+        const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+        const int srcf = f < 3 ? 3 : 0;            // H feeds the E rows, E the H rows
+        const double sg = f < 3 ? 1.0 : -1.0;
+        const double* cm = gt + e * G;
+        const double sm = MAT ? sg * up_s[e * ES + 6 * NPP + (f < 3 ? 0 : 1)] : sg;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          pc[t][mu] = sm * cm[3 * mu + b];
+          qc[t][mu] = -sm * cm[3 * mu + c];
+        }
+        vc[t] = up_s + e * ES + (srcf + c) * NPP;
+        vb[t] = up_s + e * ES + (srcf + b) * NPP;
+        fl[t] = gl + row * RSL + 4 * g4;
+      }
+      auto ld4 = [](const double* p) __attribute__((always_inline)) {
+        const doublex2 lo = *reinterpret_cast<const doublex2*>(p);
+        const doublex2 hi = *reinterpret_cast<const doublex2*>(p + 2);
+        return doublex4{lo.x, lo.y, hi.x, hi.y};
+      };
+      // operator quad q: the one loaded LA quads ago; its buffer takes quad q + LA
+      auto quad = [&](int q) __attribute__((always_inline)) {
+        const doublex4 w = wb[q % LA];
+        if (q + LA < NQ) wb[q % LA] = bq[64 * (q + LA)];
+        return w;
+      };
+#pragma unroll
+      for (int jb = 0; jb < VB; ++jb) {
+        doublex4 xc[RT], xb[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          xc[t] = ld4(vc[t] + 16 * jb + 4 * g4);
+          xb[t] = ld4(vb[t] + 16 * jb + 4 * g4);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const doublex4 w = quad(3 * jb + mu);
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(pc[t][mu] * xc[t][s] + qc[t][mu] * xb[t][s], w[s],
+                                                            acc[t], 0, 0, 0);
+          // keep each quad's loads where they are written: hoisted, the operator loads of
+          // all quads would be live at once
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+#pragma unroll
+      for (int fb = 0; fb < QF; ++fb) {
+        doublex4 xf[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) xf[t] = ld4(fl[t] + 16 * fb);
+        const doublex4 w = quad(QV + fb);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[t][s], w[s], acc[t], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int r = 0; r < VR; ++r) {
+        double xc1[RT], xb1[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          xc1[t] = vc[t][16 * VB + 4 * r + g4];
+          xb1[t] = vb[t][16 * VB + 4 * r + g4];
+        }
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu)
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(pc[t][mu] * xc1[t] + qc[t][mu] * xb1[t], w1[3 * r + mu],
+                                                          acc[t], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    // the next tile's exterior traces, then this tile's residual
+    gather(nxt, fcb[more ? par ^ 1 : par]);
+    doublex2 rs[CPT];
+    if (STAGE) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r)
+        rs[r] = __builtin_nontemporal_load(reinterpret_cast<const doublex2*>(res) +
+                                           min(size_t(tile) * TC + min(tid + r * NTH, TC - 1), chunk_last));
+    }
+    __syncthreads();   // flux rows are read: reuse them for the staging
+
+    // ---- stage the right-hand side [e][f][n] contiguously (nodes >= Np are the padding of
+    // the last column tile)
+    double* stage = gl;
+    const int col = 16 * nt + li;
+    if (col < NP) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * t + g4 + 4 * i;
+          const int f = row / E, e = row - f * E;
+          stage[(e * 6 + f) * NP + col] = acc[t][i];
+        }
+    }
+    __syncthreads();
+
+    // ---- update and write out, 16-byte chunks
+    if (full) {
+      doublex2* o2 = reinterpret_cast<doublex2*>(out + tb);
+      doublex2* r2 = reinterpret_cast<doublex2*>(res + tb);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if ((r + 1) * NTH <= TC || c < TC) {
+          const doublex2 h = reinterpret_cast<const doublex2*>(stage)[c];
+          if (STAGE) {
+            const doublex2 u = *reinterpret_cast<const doublex2*>(up_s + slot(2 * c));
+            const doublex2 rv = doublex2{ca * rs[r].x + cdt * h.x, ca * rs[r].y + cdt * h.y};
+            __builtin_nontemporal_store(rv, r2 + c);
+            __builtin_nontemporal_store(doublex2{u.x + cb * rv.x, u.y + cb * rv.y}, o2 + c);
+          } else {
+            o2[c] = h;
+          }
+        }
+      }
+    } else {
+      for (int q = tid; q < nel * 6 * NP; q += NTH) {
+        const double h = stage[q];
+        if (STAGE) {
+          const double rv = ca * res[tb + q] + cdt * h;
+          res[tb + q] = rv;
+          out[tb + q] = up_s[slot(q)] + cb * rv;
+        } else {
+          out[tb + q] = h;
+        }
+      }
+    }
+    if (tile + 2 * nwg < tend && tid < E * 4) fcb[par][tid] = pf;
+    par ^= 1;
+    __syncthreads();   // the next tile overwrites up_s, gt, fcb and gl
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // Split-BF16 form of the FP32 contraction (N = 5, 6, 7): each value x of the operand and of
 // the operator is carried as x_hi + x_lo, x_hi = bf16(x), x_lo = bf16(x - x_hi), and a
 // product is taken as x_hi y_hi + x_hi y_lo + x_lo y_hi (three v_mfma_f32_16x16x32_bf16 per
@@ -2225,6 +2588,26 @@ struct DmfmaLaunch {
 };
 
 template <int N, bool STAGE, bool MAT, bool SRC>
+hipError_t launch_wmfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
+  const int E = WDims<N>::E;
+  const int ntiles = (a.K + E - 1) / E;
+  const int nb = persistent_grid<wmfma_stage_kernel<N, STAGE, MAT, SRC>>(WDims<N>::THREADS, ntiles);
+  wmfma_stage_kernel<N, STAGE, MAT, SRC><<<nb, WDims<N>::THREADS, 0, s>>>(
+      static_cast<const double*>(a.u_in), static_cast<double*>(a.out), static_cast<double*>(a.res),
+      static_cast<const double*>(a.geo), a.fcode, static_cast<const double*>(a.mat),
+      static_cast<const double*>(ops.opfrag), ops.fmask, ops.nbrnode, a.K, ntiles,
+      STAGE ? a.a : 0.0, STAGE ? a.b : 0.0, STAGE ? a.dt : 0.0, a.src);
+  return hipGetLastError();
+}
+
+template <int N, bool STAGE, bool MAT, bool SRC>
+struct WmfmaLaunch {
+  static hipError_t run(const OpsView& o, const StageArgs& a, hipStream_t s) {
+    return launch_wmfma_v<N, STAGE, MAT, SRC>(o, a, s);
+  }
+};
+
+template <int N, bool STAGE, bool MAT, bool SRC>
 hipError_t launch_bmfma_v(const OpsView& ops, const StageArgs& a, hipStream_t s) {
   const int E = BDims<N>::E;
   const int ntiles = (a.K + E - 1) / E;
@@ -2443,7 +2826,7 @@ int opcat_words(int N) {
 
 bool mfma_order(int N) { return contraction_order(N); }
 
-bool dmfma_order(int N) { return N == 3; }
+bool dmfma_order(int N) { return N == 3 || (N >= 5 && N <= 7); }
 
 bool bf16x3_order(int N) { return N >= 5 && N <= 7; }
 
@@ -2561,7 +2944,12 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
     if (N == 7) return launch_variant<7, BmfmaLaunch>(stage, ops, a, s);
     return hipErrorInvalidValue;
   }
-  if (f64 && ops.opfrag && N == 3) return launch_variant<3, DmfmaLaunch>(stage, ops, a, s);
+  if (f64 && ops.opfrag) {
+    if (N == 3) return launch_variant<3, DmfmaLaunch>(stage, ops, a, s);
+    if (N == 5) return launch_variant<5, WmfmaLaunch>(stage, ops, a, s);
+    if (N == 6) return launch_variant<6, WmfmaLaunch>(stage, ops, a, s);
+    if (N == 7) return launch_variant<7, WmfmaLaunch>(stage, ops, a, s);
+  }
   if (!f64 && ops.opfrag) {
     if (N == 3) return launch_variant<3, SmfmaLaunch>(stage, ops, a, s);
     if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);

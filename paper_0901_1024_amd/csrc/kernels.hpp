@@ -26,8 +26,8 @@ struct OpsView {
 int opcat_words(int N);
 // Whether the FP32 MFMA stage kernel serves order N.
 bool mfma_order(int N);
-// Whether the FP64 MFMA stage kernel serves order N (it reads the operator table of the FP32
-// kernel of the same order, in FP64).
+// Whether an FP64 MFMA stage kernel serves order N (N = 3, 5, 6, 7; each reads the operator
+// table of the FP32 kernel of the same order, in FP64).
 bool dmfma_order(int N);
 // Whether the split-BF16 contraction kernel serves order N.
 bool bf16x3_order(int N);

@@ -202,7 +202,8 @@ def test_kernel_choice_is_checked_on_the_host():
     v, e = dginputs.kuhn_cube(1)
     P.Solver(v, e, 3, "f32", device=-1, tile_id=1)
     P.Solver(v, e, 3, "f64", device=-1, tile_id=2)
-    for N, prec, tid in [(4, "f32", 1), (5, "f64", 2), (2, "f32", 2), (5, "bf16x3", 1), (3, "f32", 3)]:
+    P.Solver(v, e, 5, "f64", device=-1, tile_id=2)
+    for N, prec, tid in [(4, "f32", 1), (4, "f64", 2), (2, "f32", 2), (5, "bf16x3", 1), (3, "f32", 3)]:
         with pytest.raises(P.DGError):
             P.Solver(v, e, N, prec, device=-1, tile_id=tid)
     with pytest.raises(P.DGError, match="DG_E_UNSUPPORTED"):

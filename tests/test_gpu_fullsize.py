@@ -84,14 +84,17 @@ def test_fp32_full_size_steady_state_loop(N, n, medium):
 
 
 @pytest.mark.parametrize("medium", [False, True])
-def test_fp64_contraction_kernel_full_size(medium):
-    """FP64 N = 3 on its contraction kernel at full size (8-element tiles, 355,914 = 8 *
-    44,489 + 2 elements: a ragged last tile), vacuum and medium with absorbing faces."""
-    v, e, m, u, eps, mu, fb, absorb = big_problem(3, 39)
-    say(f"case: N=3 K={m.K} f64 full size, shuffled vertices, {'medium+absorbing' if medium else 'vacuum'}")
+@pytest.mark.parametrize("N,n", [(3, 39), (5, 31), (7, 25)])
+def test_fp64_contraction_kernel_full_size(N, n, medium):
+    """FP64 on its contraction kernels at full size, 8-element tiles with a ragged last one:
+    N = 3 on 355,914 = 8 * 44,489 + 2 elements, N = 5 on 178,746 = 8 * 22,343 + 2, N = 7 on
+    93,750 = 8 * 11,718 + 6 (every workgroup takes many tiles); vacuum and medium with
+    absorbing faces."""
+    v, e, m, u, eps, mu, fb, absorb = big_problem(N, n)
+    say(f"case: N={N} K={m.K} f64 full size, shuffled vertices, {'medium+absorbing' if medium else 'vacuum'}")
     kw = dict(eps=eps, mu=mu, absorb=absorb) if medium else {}
-    s = P.Solver(v, e, 3, "f64", reorder=1, **(dict(eps=eps, mu=mu, face_bc=fb) if medium else {}))
-    check_sampled(s, m, u, kw, "f64", 700, 10, seed=140)
+    s = P.Solver(v, e, N, "f64", reorder=1, **(dict(eps=eps, mu=mu, face_bc=fb) if medium else {}))
+    check_sampled(s, m, u, kw, "f64", 700, 10, seed=140 + N)
     s.free()
 
 
