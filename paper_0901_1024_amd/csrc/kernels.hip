@@ -1713,9 +1713,6 @@ __global__ __launch_bounds__(WDims<N>::THREADS) __attribute__((amdgpu_waves_per_
             for (int t = 0; t < RT; ++t)
               acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(pc[t][mu] * xc[t][s] + qc[t][mu] * xb[t][s], w[s],
                                                             acc[t], 0, 0, 0);
-          // keep each quad's loads where they are written: hoisted, the operator loads of
-          // all quads would be live at once
-          __builtin_amdgcn_sched_barrier(0);
         }
       }
 #pragma unroll
@@ -1728,7 +1725,6 @@ __global__ __launch_bounds__(WDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int t = 0; t < RT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[t][s], w[s], acc[t], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int r = 0; r < VR; ++r) {
