@@ -753,6 +753,11 @@ struct HDims {
   // exterior traces gathered one tile ahead (registers live across the contraction) where the
   // register file allows two waves per SIMD; otherwise at the start of the flux phase
   static constexpr bool AHEAD = N == 5;
+  // N = 7: the operator strip (126 VGPRs per lane) is streamed from L2 per tile instead of kept
+  // resident, as in the FP64 kernel of these orders (1809 against 1951 us per stage at K =
+  // 196,608; at N = 5, 6 the resident strip is faster: 464 / 1214 against 503 / 1388 us)
+  static constexpr bool STREAM = N == 7;
+  static constexpr int LA = STREAM ? 3 : 1;           // streamed quads in flight
   static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
   static_assert(TW % 4 == 0, "a tile is a whole number of float4 chunks");
   static_assert(NPP == Np, "rows need no padding: 16-byte chunks of a tile map to the LDS rows");
@@ -798,10 +803,11 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   int tile = xcd * TX + wj;
   if (tile >= tend) return;
 
-  // once per workgroup: this wave's operator fragments (registers) and the node tables
-  floatx4 bq[NQ];
+  // once per workgroup: this wave's operator fragments (registers, unless streamed) and the
+  // node tables
+  floatx4 bq[D::STREAM ? 1 : NQ];
   float bs[3 * VR > 0 ? 3 * VR : 1];
-  {
+  if constexpr (!D::STREAM) {
     const floatx4* src = reinterpret_cast<const floatx4*>(opf + size_t(nt) * KS * 64) + lane;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) bq[q] = src[64 * q];
@@ -939,6 +945,34 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
       }
     }
     __syncthreads();
+    // streamed operator: the first quads and the singles of this wave's strip, issued before
+    // the next tile's prefetch; the base address passes through an empty asm so the loads stay
+    // in the tile loop
+    constexpr int LA = D::LA;
+    floatx4 wb[LA];
+    if constexpr (D::STREAM) {
+      const float* opw = opf + size_t(nt) * KS * 64;
+      asm volatile("" : "+s"(opw));
+      const floatx4* bqs = reinterpret_cast<const floatx4*>(opw) + lane;
+#pragma unroll
+      for (int i = 0; i < LA; ++i) wb[i] = bqs[64 * i];
+#pragma unroll
+      for (int i = 0; i < 3 * VR; ++i) bs[i] = opw[NQ * 256 + 64 * i + lane];
+    }
+    // operator quad q: resident, or the one loaded LA quads ago (its buffer takes quad q + LA)
+    auto quad = [&](int q) __attribute__((always_inline)) {
+      if constexpr (D::STREAM) {
+        const floatx4 w = wb[q % LA];
+        if (q + LA < NQ) {
+          const float* opw = opf + size_t(nt) * KS * 64;
+          asm volatile("" : "+s"(opw));
+          wb[q % LA] = reinterpret_cast<const floatx4*>(opw)[64 * (q + LA) + lane];
+        }
+        return w;
+      } else {
+        return bq[q];
+      }
+    };
     if (STAGE) {
 #pragma unroll
       for (int r = 0; r < CPT; ++r)
@@ -985,7 +1019,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         }
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu) {
-          const floatx4 w = bq[3 * jb + mu];
+          const floatx4 w = quad(3 * jb + mu);
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const float ws = s == 0 ? w.x : s == 1 ? w.y : s == 2 ? w.z : w.w;
@@ -1006,7 +1040,7 @@ __global__ __launch_bounds__(HDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         floatx4 xf[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) xf[t] = *reinterpret_cast<const floatx4*>(fl[t] + 16 * fb);
-        const floatx4 w = bq[QV + fb];
+        const floatx4 w = quad(QV + fb);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const float ws = s == 0 ? w.x : s == 1 ? w.y : s == 2 ? w.z : w.w;
