@@ -39,7 +39,7 @@ extern "C" {
 #define DG_OK 0
 #define DG_E_ARG (-1)         /* invalid argument (NULL pointer, bad size, bad option) */
 #define DG_E_MESH (-2)        /* invalid mesh: degenerate element, face shared by > 2 elements */
-#define DG_E_UNSUPPORTED (-3) /* order outside 1..7, unknown precision, DG_BF16X3 outside 5..7 */
+#define DG_E_UNSUPPORTED (-3) /* order outside 1..9, unknown precision, DG_BF16X3 outside 5..7 */
 #define DG_E_OOM (-4)         /* device allocation failed or the workspace is too small */
 #define DG_E_HIP (-5)         /* a HIP runtime call failed; message in dg_last_error() */
 #define DG_E_STATE (-6)       /* handle has no device state (built with device = -1) */
@@ -71,7 +71,7 @@ typedef struct {
 } dg_mesh;
 
 typedef struct {
-  int32_t order;     /* polynomial order N, 1..7 */
+  int32_t order;     /* polynomial order N, 1..9 (matrix-core kernels at 3..7) */
   int32_t precision; /* dg_precision */
   int32_t reorder;   /* 0 = keep user element order internally, 1 = Morton locality order */
   int32_t device;    /* HIP device ordinal, or -1 for a host-only handle (builder outputs

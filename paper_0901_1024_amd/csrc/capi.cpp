@@ -39,7 +39,7 @@ struct Layout {
   size_t state = 0;   // bytes of one canonical [6][K][Np] array
   size_t istate = 0;  // bytes of one internal [K][6][S] array (S = dgk::row_stride)
   size_t off_u0, off_u1, off_res, off_tmp, off_geo, off_fcode, off_ops, off_fmask, off_nbr,
-      off_elem_of, off_pos_of, off_partial, off_opcat, off_mat, off_geo_dt, off_mat_dt, off_src,
+      off_pos_of, off_partial, off_opcat, off_mat, off_geo_dt, off_mat_dt, off_src,
       off_phase, total;
   size_t opcat_bytes = 0, mat_bytes = 0, geo_dt_bytes = 0, mat_dt_bytes = 0, src_bytes = 0, phase_bytes = 0;
 };
@@ -106,7 +106,6 @@ Layout make_layout(int K, int N, int Np, int Nfp, int prec, bool material, bool 
   L.off_ops = take((size_t(4) * Np * Np + size_t(Np) * 4 * Nfp) * ts);
   L.off_fmask = take(size_t(4) * Nfp * sizeof(int32_t));
   L.off_nbr = take(size_t(96) * Nfp * sizeof(int32_t));
-  L.off_elem_of = take(size_t(K) * sizeof(int32_t));
   L.off_pos_of = take(size_t(K) * sizeof(int32_t));
   L.off_partial = take(size_t((K + dgk::kEnergyBlockElems - 1) / dgk::kEnergyBlockElems) * sizeof(double));
   L.opcat_bytes = opfrag_bytes_for(N, prec, tile_id);
@@ -137,7 +136,7 @@ int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
   if (!mesh || !opts) return fail(DG_E_ARG, "mesh and opts must not be NULL");
   if (!mesh->vxyz || !mesh->etov) return fail(DG_E_ARG, "vxyz and etov must not be NULL");
   if (mesh->K <= 0 || mesh->nverts < 4) return fail(DG_E_ARG, "empty mesh");
-  if (opts->order < 1 || opts->order > 7) return fail(DG_E_UNSUPPORTED, "order must be in 1..7");
+  if (opts->order < 1 || opts->order > 9) return fail(DG_E_UNSUPPORTED, "order must be in 1..9");
   if (opts->precision != DG_F64 && opts->precision != DG_F32 && opts->precision != DG_BF16X3)
     return fail(DG_E_UNSUPPORTED, "unknown precision");
   if (opts->precision == DG_BF16X3 && !dgk::bf16x3_order(opts->order))
@@ -307,7 +306,6 @@ int upload(dg_handle* h, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_fmask), R.Fmask.data(), R.Fmask.size() * 4, hipMemcpyHostToDevice, s));
   std::vector<int32_t> nbr(R.nbr_node.begin(), R.nbr_node.end());
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_nbr), nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_elem_of), M.elem_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_pos_of), M.pos_of.data(), size_t(K) * 4, hipMemcpyHostToDevice, s));
   if (h->nscat) {   // no incident wave until dg_set_incident: scatterer faces act as walls
     HIP_TRY(hipMemsetAsync(h->at(h->lay.off_src), 0, h->lay.src_bytes, s));
@@ -663,9 +661,9 @@ int dg_set_fields(dg_handle* h, const void* u, int on_device, void* stream) {
     HIP_TRY(hipMemcpyAsync(h->at(h->lay.off_tmp), u, h->lay.state, hipMemcpyHostToDevice, s));
     src = h->at(h->lay.off_tmp);
   }
-  HIP_TRY(dgk::launch_to_internal(h->f64(), src, h->u(h->cur),
-                                  static_cast<const int32_t*>(h->at(h->lay.off_elem_of)), h->K, h->Np, h->S, s));
-  HIP_TRY(hipMemsetAsync(h->at(h->lay.off_res), 0, h->lay.istate, s));
+  HIP_TRY(dgk::launch_to_internal(h->N, h->f64(), src, h->u(h->cur),
+                                  static_cast<const int32_t*>(h->at(h->lay.off_pos_of)), h->K, s));
+  HIP_TRY(dgk::launch_zero(h->at(h->lay.off_res), h->lay.istate, s));
   if (!on_device) HIP_TRY(hipStreamSynchronize(s));
   return DG_OK;
 }
@@ -678,8 +676,8 @@ int dg_get_fields(const dg_handle* h, void* u, int on_device, void* stream) {
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* dst = on_device ? u : h->at(h->lay.off_tmp);
-  HIP_TRY(dgk::launch_to_canonical(h->f64(), h->u(h->cur), dst,
-                                   static_cast<const int32_t*>(h->at(h->lay.off_pos_of)), h->K, h->Np, h->S, s));
+  HIP_TRY(dgk::launch_to_canonical(h->N, h->f64(), h->u(h->cur), dst,
+                                   static_cast<const int32_t*>(h->at(h->lay.off_pos_of)), h->K, s));
   if (!on_device) {
     HIP_TRY(hipMemcpyAsync(u, dst, h->lay.state, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -696,12 +694,12 @@ int dg_rhs(dg_handle* h, const void* u_dev, void* rhs_dev, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* in = h->u(1 - h->cur);  // the spare state buffer is free between steps
   void* out = h->at(h->lay.off_tmp);
-  HIP_TRY(dgk::launch_to_internal(h->f64(), u_dev, in, static_cast<const int32_t*>(h->at(h->lay.off_elem_of)),
-                                  h->K, h->Np, h->S, s));
+  HIP_TRY(dgk::launch_to_internal(h->N, h->f64(), u_dev, in, static_cast<const int32_t*>(h->at(h->lay.off_pos_of)),
+                                  h->K, s));
   rc = stage_launch(h, false, in, out, 0, 0, 0, s);
   if (rc) return rc;
-  HIP_TRY(dgk::launch_to_canonical(h->f64(), out, rhs_dev, static_cast<const int32_t*>(h->at(h->lay.off_pos_of)),
-                                   h->K, h->Np, h->S, s));
+  HIP_TRY(dgk::launch_to_canonical(h->N, h->f64(), out, rhs_dev, static_cast<const int32_t*>(h->at(h->lay.off_pos_of)),
+                                   h->K, s));
   return DG_OK;
 }
 

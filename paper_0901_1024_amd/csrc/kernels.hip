@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstdint>
 #include <mutex>
 
 #include "host/meshbuild.hpp"
@@ -1491,13 +1492,13 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 // operator strip is 2 KD VGPRs per lane (264 at N = 7), too large to keep resident, and the
 // whole operator (100-480 KB) does not fit in LDS beside the tile, so each wave streams its
 // strip from L2 (the table is a few hundred KB and every workgroup of an XCD reads it) with
-// LA quads in flight; each quad feeds RT x 4 matrix steps, which bounds the L2 traffic at
-// 8 / (4 RT) bytes per lane and multiply. The first quads are issued before the next tile's
-// prefetch, so their waits do not include those HBM loads. Exterior traces of the next tile
-// are gathered after the contraction (their registers are not live across it); the residual
-// is loaded after them, for the update. Issue priorities and nontemporal residual and state
-// I/O as in the other contraction kernels. Result layout: lane (li, g4) register i = row
-// 16 t + g4 + 4 i of row tile t, node 16 nt + li.
+// LA quads in flight; each operator value a lane loads (8 bytes) feeds RT matrix steps of 16
+// multiply-adds per lane, i.e. 1/6 byte of L2 reads per lane and multiply-add. The first quads
+// are issued before the next tile's prefetch, so their waits do not include those HBM loads.
+// Exterior traces of the next tile are gathered after the contraction (their registers are not
+// live across it); the residual is loaded after them, for the update. Issue priorities and
+// nontemporal residual and state I/O as in the other contraction kernels. Result layout: lane
+// (li, g4) register i = row 16 t + g4 + 4 i of row tile t, node 16 nt + li.
 template <int N>
 struct WDims {
   using H = HDims<N>;                                 // tile, wave and operator geometry
@@ -2710,30 +2711,106 @@ hipError_t launch_stage_t(bool stage, const OpsView& ops, const StageArgs& a, hi
   return hipGetLastError();
 }
 
-template <typename T>
-__global__ void to_internal_kernel(const T* __restrict__ canon, T* __restrict__ internal,
-                                   const int32_t* __restrict__ elem_of, int K, int Np, int S) {
-  const int64_t total = int64_t(K) * 6 * S;
-  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < total;
-       q += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = q / (6 * S);
-    const int rem = int(q - i * 6 * S);
-    const int c = rem / S, n = rem - c * S;
-    internal[q] = n < Np ? canon[(int64_t(c) * K + elem_of[i]) * Np + n] : T(0);
+// Canonical [6][K][Np] <-> internal [K][6][S] in chunks of CE consecutive user elements: the
+// chunk's six canonical field blocks (CE Np contiguous words each) are read or written
+// coalesced, and each element's internal block (6 S contiguous words at its internal position
+// pos_of[e]) is written or read whole; the transposition happens in LDS ([CE][6][S]). Np, S
+// and CE are compile-time constants, so the index arithmetic has no runtime divisions, and
+// each phase issues all of a thread's loads before its first use (R1 / R2 rounds unrolled),
+// so a thread keeps up to 32 loads in flight. Index arithmetic in I (32-bit where the arrays
+// fit).
+template <typename T, int N>
+struct PermDims {
+  static constexpr int Np = Dims<N>::Np, S = kRowStride<T, N>, RS = 6 * S;
+  static constexpr int CE0 = (32 * 1024) / int(RS * sizeof(T));
+  static constexpr int CE = CE0 < 1 ? 1 : (CE0 > 64 ? 64 : CE0);   // LDS tile <= 32 KB
+  static constexpr int BLK = CE * Np;
+  static constexpr int R1 = (6 * BLK + kThreads - 1) / kThreads;   // canonical-side rounds
+  static constexpr int R2 = (CE * RS + kThreads - 1) / kThreads;   // internal-side rounds
+};
+
+template <typename T, int N, typename I>
+__global__ __launch_bounds__(kThreads) void to_internal_kernel(const T* __restrict__ canon,
+                                                               T* __restrict__ internal,
+                                                               const int32_t* __restrict__ pos_of, int K) {
+  using D = PermDims<T, N>;
+  constexpr int NP = D::Np, S = D::S, RS = D::RS, CE = D::CE, BLK = D::BLK, R1 = D::R1, R2 = D::R2;
+  static_assert(CE <= kThreads, "one position per thread");
+  __shared__ __align__(16) T tile[CE * RS];
+  __shared__ int32_t pos_s[CE];
+  const int tid = threadIdx.x;
+  for (int e0 = blockIdx.x * CE; e0 < K; e0 += gridDim.x * CE) {
+    const int ne = min(CE, K - e0);
+    T v[R1];
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+      const int q = tid + k * kThreads;
+      const int c = q / BLK, r = q - c * BLK, j = r / NP;
+      v[k] = (q < 6 * BLK && j < ne) ? canon[(I(c) * K + e0) * NP + r] : T(0);
+    }
+    // the chunk's internal positions, read after the field loads (in-order completion: their
+    // wait covers those loads, which are needed next anyway) and kept in LDS, so that the
+    // stores below do not wait on a global load each
+    if (tid < ne) pos_s[tid] = pos_of[e0 + tid];
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+      const int q = tid + k * kThreads;
+      const int c = q / BLK, r = q - c * BLK, j = r / NP, n = r - j * NP;
+      if (q < 6 * BLK) tile[j * RS + c * S + n] = v[k];
+    }
+    if constexpr (S > NP)
+      for (int q = tid; q < 6 * CE * (S - NP); q += kThreads) {
+        const int row = q / (S - NP);
+        tile[row * S + NP + (q - row * (S - NP))] = T(0);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R2; ++k) {
+      const int q = tid + k * kThreads, j = q / RS;
+      if (q < CE * RS && j < ne) internal[I(pos_s[j]) * RS + (q - j * RS)] = tile[q];
+    }
+    __syncthreads();
   }
 }
 
-template <typename T>
-__global__ void to_canonical_kernel(const T* __restrict__ internal, T* __restrict__ canon,
-                                    const int32_t* __restrict__ pos_of, int K, int Np, int S) {
-  const int64_t total = int64_t(K) * 6 * Np;
-  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < total;
-       q += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t c = q / (int64_t(K) * Np);
-    const int64_t rem = q - c * K * Np;
-    const int64_t k = rem / Np;
-    const int n = int(rem - k * Np);
-    canon[q] = internal[(int64_t(pos_of[k]) * 6 + c) * S + n];
+template <typename T, int N, typename I>
+__global__ __launch_bounds__(kThreads) void to_canonical_kernel(const T* __restrict__ internal,
+                                                                T* __restrict__ canon,
+                                                                const int32_t* __restrict__ pos_of, int K) {
+  using D = PermDims<T, N>;
+  constexpr int NP = D::Np, S = D::S, RS = D::RS, CE = D::CE, BLK = D::BLK, R1 = D::R1, R2 = D::R2;
+  static_assert(CE <= kThreads, "one position per thread");
+  __shared__ __align__(16) T tile[CE * RS];
+  __shared__ int32_t pos_s[CE];
+  const int tid = threadIdx.x;
+  const int stride = gridDim.x * CE;
+  // internal positions of the first chunk; those of the next one are loaded during each chunk
+  int pn = 0;
+  if (tid < CE && blockIdx.x * CE + tid < K) pn = pos_of[blockIdx.x * CE + tid];
+  for (int e0 = blockIdx.x * CE; e0 < K; e0 += stride) {
+    const int ne = min(CE, K - e0);
+    if (tid < CE) pos_s[tid] = pn;
+    __syncthreads();
+    T v[R2];
+#pragma unroll
+    for (int k = 0; k < R2; ++k) {
+      const int q = tid + k * kThreads, j = q / RS;
+      v[k] = (q < CE * RS && j < ne) ? internal[I(pos_s[j]) * RS + (q - j * RS)] : T(0);
+    }
+    if (tid < CE && e0 + stride + tid < K) pn = pos_of[e0 + stride + tid];
+#pragma unroll
+    for (int k = 0; k < R2; ++k) {
+      const int q = tid + k * kThreads;
+      if (q < CE * RS) tile[q] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+      const int q = tid + k * kThreads;
+      const int c = q / BLK, r = q - c * BLK, j = r / NP, n = r - j * NP;
+      if (q < 6 * BLK && j < ne) canon[(I(c) * K + e0) * NP + r] = tile[j * RS + c * S + n];
+    }
+    __syncthreads();
   }
 }
 
@@ -2817,6 +2894,8 @@ hipError_t dispatch_stage(int N, bool stage, const OpsView& o, const StageArgs& 
     case 5: return valu_stage<T, 5>(stage, o, a, s);
     case 6: return valu_stage<T, 6>(stage, o, a, s);
     case 7: return valu_stage<T, 7>(stage, o, a, s);
+    case 8: return valu_stage<T, 8>(stage, o, a, s);
+    case 9: return valu_stage<T, 9>(stage, o, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -2832,6 +2911,8 @@ hipError_t dispatch_energy(int N, const void* u, const void* M, const void* geo,
     case 5: return launch_energy_t<T, 5>(u, M, geo, mat, K, p, s);
     case 6: return launch_energy_t<T, 6>(u, M, geo, mat, K, p, s);
     case 7: return launch_energy_t<T, 7>(u, M, geo, mat, K, p, s);
+    case 8: return launch_energy_t<T, 8>(u, M, geo, mat, K, p, s);
+    case 9: return launch_energy_t<T, 9>(u, M, geo, mat, K, p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -2990,34 +3071,78 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
   return f64 ? dispatch_stage<double>(N, stage, ops, a, s) : dispatch_stage<float>(N, stage, ops, a, s);
 }
 
-hipError_t launch_to_internal(bool f64, const void* canon, void* internal, const int32_t* elem_of,
-                              int K, int Np, int S, hipStream_t s) {
-  const int g = grid_for(int64_t(K) * 6 * S);
-  if (f64)
-    to_internal_kernel<double><<<g, kThreads, 0, s>>>(static_cast<const double*>(canon),
-                                                      static_cast<double*>(internal), elem_of, K, Np, S);
-  else
-    to_internal_kernel<float><<<g, kThreads, 0, s>>>(static_cast<const float*>(canon),
-                                                     static_cast<float*>(internal), elem_of, K, Np, S);
+namespace {
+template <typename T, int N, bool TO_INTERNAL>
+hipError_t launch_permute_t(const void* from, void* to, const int32_t* pos_of, int K, hipStream_t s) {
+  using D = PermDims<T, N>;
+  if (K <= 0) return hipSuccess;
+  const int64_t chunks = (int64_t(K) + D::CE - 1) / D::CE;
+  const int g = int(chunks < 8192 ? chunks : 8192);
+  const bool narrow = int64_t(K) * D::RS < INT32_MAX;
+  auto* f = static_cast<const T*>(from);
+  auto* t = static_cast<T*>(to);
+  if (TO_INTERNAL) {
+    if (narrow) to_internal_kernel<T, N, int32_t><<<g, kThreads, 0, s>>>(f, t, pos_of, K);
+    else to_internal_kernel<T, N, int64_t><<<g, kThreads, 0, s>>>(f, t, pos_of, K);
+  } else {
+    if (narrow) to_canonical_kernel<T, N, int32_t><<<g, kThreads, 0, s>>>(f, t, pos_of, K);
+    else to_canonical_kernel<T, N, int64_t><<<g, kThreads, 0, s>>>(f, t, pos_of, K);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, const int32_t* pos_of,
-                               int K, int Np, int S, hipStream_t s) {
-  const int g = grid_for(int64_t(K) * 6 * Np);
-  if (f64)
-    to_canonical_kernel<double><<<g, kThreads, 0, s>>>(static_cast<const double*>(internal),
-                                                       static_cast<double*>(canon), pos_of, K, Np, S);
-  else
-    to_canonical_kernel<float><<<g, kThreads, 0, s>>>(static_cast<const float*>(internal),
-                                                      static_cast<float*>(canon), pos_of, K, Np, S);
-  return hipGetLastError();
+template <typename T, bool TO_INTERNAL>
+hipError_t launch_permute(int N, const void* from, void* to, const int32_t* pos_of, int K, hipStream_t s) {
+  switch (N) {
+    case 1: return launch_permute_t<T, 1, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 2: return launch_permute_t<T, 2, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 3: return launch_permute_t<T, 3, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 4: return launch_permute_t<T, 4, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 5: return launch_permute_t<T, 5, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 6: return launch_permute_t<T, 6, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 7: return launch_permute_t<T, 7, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 8: return launch_permute_t<T, 8, TO_INTERNAL>(from, to, pos_of, K, s);
+    case 9: return launch_permute_t<T, 9, TO_INTERNAL>(from, to, pos_of, K, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_to_internal(int N, bool f64, const void* canon, void* internal, const int32_t* pos_of,
+                              int K, hipStream_t s) {
+  return f64 ? launch_permute<double, true>(N, canon, internal, pos_of, K, s)
+             : launch_permute<float, true>(N, canon, internal, pos_of, K, s);
+}
+
+hipError_t launch_to_canonical(int N, bool f64, const void* internal, void* canon, const int32_t* pos_of,
+                               int K, hipStream_t s) {
+  return f64 ? launch_permute<double, false>(N, internal, canon, pos_of, K, s)
+             : launch_permute<float, false>(N, internal, canon, pos_of, K, s);
 }
 
 hipError_t launch_energy(int N, bool f64, const void* u, const void* M, const void* geo, const void* mat,
                          int K, double* partial, hipStream_t s) {
   return f64 ? dispatch_energy<double>(N, u, M, geo, mat, K, partial, s)
              : dispatch_energy<float>(N, u, M, geo, mat, K, partial, s);
+}
+
+namespace {
+__global__ __launch_bounds__(kThreads) void zero_kernel(uint4* __restrict__ p, size_t n16, uint8_t* __restrict__ tail,
+                                                        int ntail) {
+  const size_t stride = size_t(gridDim.x) * kThreads;
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n16; i += stride) p[i] = uint4{0u, 0u, 0u, 0u};
+  if (blockIdx.x == 0 && int(threadIdx.x) < ntail) tail[threadIdx.x] = 0;
+}
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (reinterpret_cast<uintptr_t>(p) % 16) return hipErrorInvalidValue;
+  const size_t n16 = bytes / 16;
+  const int ntail = int(bytes % 16);
+  const int g = grid_for(int64_t(n16 > 0 ? n16 : 1));
+  zero_kernel<<<g, kThreads, 0, s>>>(static_cast<uint4*>(p), n16, static_cast<uint8_t*>(p) + n16 * 16, ntail);
+  return hipGetLastError();
 }
 
 hipError_t launch_advance_clock(double* rec, double dt, hipStream_t s) {

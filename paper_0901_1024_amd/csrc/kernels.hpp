@@ -72,12 +72,16 @@ struct StageArgs {
 hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const StageArgs& a,
                         hipStream_t s);
 
-// Canonical [6][K][Np] <-> internal [K][6][S] (internal position i holds user element
-// elem_of[i]; to_internal writes the pad words as zero).
-hipError_t launch_to_internal(bool f64, const void* canon, void* internal, const int32_t* elem_of,
-                              int K, int Np, int S, hipStream_t s);
-hipError_t launch_to_canonical(bool f64, const void* internal, void* canon, const int32_t* pos_of,
-                               int K, int Np, int S, hipStream_t s);
+// Canonical [6][K][Np] <-> internal [K][6][S] (user element e sits at internal position
+// pos_of[e]; to_internal writes the pad words as zero).
+hipError_t launch_to_internal(int N, bool f64, const void* canon, void* internal, const int32_t* pos_of,
+                              int K, hipStream_t s);
+hipError_t launch_to_canonical(int N, bool f64, const void* internal, void* canon, const int32_t* pos_of,
+                               int K, hipStream_t s);
+
+// Zero `bytes` bytes at p (16-byte aligned) with a kernel: a memset node recorded into a graph
+// that a caller captures has given wrong results on replay, a kernel node has not.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Advance the step's start time in the incident record by dt (after the fifth stage).
 hipError_t launch_advance_clock(double* rec, double dt, hipStream_t s);

@@ -58,7 +58,7 @@ def candidates(order, precision):
     return out
 
 
-def tune(orders=range(1, 8), precisions=("f32", "f64"), sizes=(750, 6000, 48000, 384000), steps=20,
+def tune(orders=range(1, 10), precisions=("f32", "f64"), sizes=(750, 6000, 48000, 384000), steps=20,
          path=None, device=0, log=print):
     """Time every candidate kernel per (precision, order, size) and write the table."""
     import numpy as np

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("N", range(1, 8))
+@pytest.mark.parametrize("N", range(1, 10))
 def test_builder_operators_match_oracle(N):
     v, e = dginputs.kuhn_cube(1)
     s = P.Solver(v, e, N, device=-1)
@@ -53,7 +53,7 @@ def test_builder_maps_are_bit_identical_to_oracle(N, n, jitter, permute):
     assert abs(s.stable_dt(0.5) - dt_o) <= 1e-14 * dt_o
 
 
-@pytest.mark.parametrize("N", range(1, 8))
+@pytest.mark.parametrize("N", range(1, 10))
 def test_builder_maps_on_shuffled_vertex_order(N):
     """Every element lists its vertices in a random order of its own (half come out negatively
     oriented), so the mesh reaches all 48 (face, neighbour face, vertex rotation) combinations
@@ -92,8 +92,9 @@ def test_setup_query_sizes_the_workspace():
 
 def test_errors_are_reported_not_raised_in_c():
     v, e = dginputs.kuhn_cube(1)
-    with pytest.raises(P.DGError, match="DG_E_UNSUPPORTED"):
-        P.Solver(v, e, 8, device=-1)
+    for N in (0, 10):
+        with pytest.raises(P.DGError, match="DG_E_UNSUPPORTED"):
+            P.Solver(v, e, N, device=-1)
     with pytest.raises(P.DGError, match="DG_E_MESH"):
         P.Solver(v, np.concatenate([e, e[:1]]), 2, device=-1)
     bad = e.copy()

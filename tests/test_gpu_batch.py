@@ -1,9 +1,10 @@
 """The batched form on the GPU: one handle holding several meshes (different K, geometry,
-face conditions, materials) equals one handle per mesh. In FP64 the right-hand side is bitwise
-equal (the VALU kernel's per-element arithmetic does not depend on the element's position);
-the FP32 contraction kernel may round an element's face fluxes differently at another position
-in its tile, so there the bound is 1e-6. RK steps with per-mesh time steps agree to the parity
-tolerances (the step is folded into the geometric records, which changes the rounding, not the
+face conditions, materials) equals one handle per mesh. On the element-wise kernel (FP64 N = 2)
+the right-hand side is bitwise equal (its per-element arithmetic does not depend on the
+element's position); a contraction kernel may round an element's face fluxes differently at
+another position in its tile, so there the bound is 1e-6 in FP32 and 1e-13 in FP64 (N = 5 on
+the FP64 high-order kernel). RK steps with per-mesh time steps agree to the parity tolerances
+(the step is folded into the geometric records, which changes the rounding, not the
 operator)."""
 import numpy as np
 import pytest
@@ -32,7 +33,7 @@ def batch_meshes(prec):
     return out
 
 
-@pytest.mark.parametrize("prec,N", [("f64", 2), ("f32", 3), ("f32", 4), ("f32", 5)])
+@pytest.mark.parametrize("prec,N", [("f64", 2), ("f64", 5), ("f32", 3), ("f32", 4), ("f32", 5)])
 def test_batch_equals_one_handle_per_mesh(prec, N):
     say(f"case: batch of 4 meshes N={N} {prec}")
     meshes = batch_meshes(prec)
@@ -45,10 +46,10 @@ def test_batch_equals_one_handle_per_mesh(prec, N):
     rb = gpu_rhs(b, ub)
     for i, s in enumerate(singles):
         r1 = gpu_rhs(s, us[i])
-        if prec == "f64":
+        if prec == "f64" and N == 2:
             assert np.array_equal(rb[:, b.mesh_slice(i)], r1)
         else:
-            assert rel_l2(rb[:, b.mesh_slice(i)], r1) <= 1e-6
+            assert rel_l2(rb[:, b.mesh_slice(i)], r1) <= (1e-13 if prec == "f64" else 1e-6)
     dts = b.stable_dts(0.5)
     b.set_dts(dts)
     b.set_fields(ub)

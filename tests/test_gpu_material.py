@@ -28,7 +28,7 @@ def medium_problem(N, n, seed=21):
     return v, e, m, u0, eps, mu, fb, absorb
 
 
-@pytest.mark.parametrize("N", range(1, 8))
+@pytest.mark.parametrize("N", range(1, 10))
 def test_medium_absorbing_fp64_all_orders(N):
     say(f"case: medium+absorbing N={N} K=48 f64")
     v, e, m, u0, eps, mu, fb, absorb = medium_problem(N, 2)

@@ -46,7 +46,7 @@ def test_cavity_n3_fp64_rhs_and_twenty_steps():
     assert abs(e20 - W.energy(m, uo)) <= 1e-12 * e0
 
 
-@pytest.mark.parametrize("N", range(1, 8))
+@pytest.mark.parametrize("N", range(1, 10))
 def test_all_orders_fp64_jittered_permuted(N):
     """162 tets (ragged last tile for every order), jittered and permuted, smooth fields."""
     say(f"case: N={N} K=162 f64 jitter+permute")
@@ -64,10 +64,11 @@ def test_all_orders_fp64_jittered_permuted(N):
     assert rel_l2(ug, uo) <= TOL["f64"] and max_rel(ug, uo) <= MAX_TOL["f64"]
 
 
-@pytest.mark.parametrize("N,n", [(2, 3), (3, 3), (4, 3), (4, 4), (5, 3), (5, 4), (6, 3), (6, 4), (7, 2)])
+@pytest.mark.parametrize("N,n", [(2, 3), (3, 3), (4, 3), (4, 4), (5, 3), (5, 4), (6, 3), (6, 4), (7, 2),
+                                 (8, 2), (9, 2)])
 def test_fp32_orders_small_mesh(N, n):
     """K = 162 leaves a ragged last tile of every tile size; K = 384 fills them. N = 4 runs on
-    the 16-element MFMA kernel, N = 3, 5, 6, 7 on 8-element ones, N = 2 on the VALU one."""
+    the 16-element MFMA kernel, N = 3, 5, 6, 7 on 8-element ones, N = 2, 8, 9 on the VALU one."""
     say(f"case: N={N} K={6 * n ** 3} f32 jitter+permute")
     v, e, m, u0 = problem(N, n, jitter=0.15, permute=True)
     s = P.Solver(v, e, N, "f32", reorder=1)

@@ -103,7 +103,7 @@ def test_basis_gradient_matches_difference_quotient(N):
         assert np.max(np.abs(fd - grad)) < 1e-6 * max(1.0, np.max(np.abs(grad)))
 
 
-@pytest.mark.parametrize("N", range(1, 8))
+@pytest.mark.parametrize("N", range(1, 10))
 def test_D_is_exact_on_polynomials_of_degree_N(N):
     ref = R.ref_element(N)
     r, s, t = ref.rst.T
