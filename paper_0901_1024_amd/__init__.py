@@ -154,8 +154,9 @@ def _opts_struct(order, precision, reorder, device, checks=0, tile_id=0):
 
 def _tile_option(tile_id, order, precision, K):
     """tile_id: None or 0 = the library's default kernel, 1 = element-wise, 2 = contraction,
-    "auto" = the autotuner's choice for this order, precision and mesh size (paper_0901_1024_amd.tune;
-    the default when its table has no entry)."""
+    3 = contraction with 16-element tiles (FP32 N = 3), "auto" = the autotuner's choice for this
+    order, precision and mesh size (paper_0901_1024_amd.tune; the default when its table has no
+    entry)."""
     if tile_id is None:
         return 0
     if tile_id == "auto":

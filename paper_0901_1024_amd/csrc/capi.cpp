@@ -59,7 +59,7 @@ int resolve_tile(int N, int prec, int tile_id) {
 }
 
 size_t opfrag_bytes_for(int N, int prec, int tile_id = 0) {
-  if (resolve_tile(N, prec, tile_id) != 2) return 0;
+  if (resolve_tile(N, prec, tile_id) < 2) return 0;
   if (prec == DG_BF16X3) return size_t(dgk::bopcat_words(N)) * 2;
   const bool used = prec == DG_F32 ? dgk::mfma_order(N) : dgk::dmfma_order(N);
   return used ? size_t(dgk::opcat_words(N)) * (prec == DG_F64 ? 8 : 4) : 0;
@@ -143,7 +143,9 @@ int check_inputs(const dg_mesh* mesh, const dg_opts* opts) {
     return fail(DG_E_UNSUPPORTED, "the split-BF16 contraction serves orders 5..7");
   if (opts->reorder < 0 || opts->reorder > 1) return fail(DG_E_ARG, "reorder must be 0 or 1");
   if (opts->checks < 0) return fail(DG_E_ARG, "checks must be >= 0");
-  if (opts->tile_id < 0 || opts->tile_id > 2) return fail(DG_E_ARG, "tile_id must be 0, 1 or 2");
+  if (opts->tile_id < 0 || opts->tile_id > 3) return fail(DG_E_ARG, "tile_id must be 0, 1, 2 or 3");
+  if (opts->tile_id == 3 && !(opts->precision == DG_F32 && opts->order == 3))
+    return fail(DG_E_UNSUPPORTED, "16-element contraction tiles serve FP32 N = 3 only");
   if (opts->tile_id == 2 && !contraction_kernel(opts->order, opts->precision))
     return fail(DG_E_UNSUPPORTED, "no contraction kernel for this order and precision");
   if (opts->tile_id == 1 && (opts->precision == DG_BF16X3 ||
@@ -181,6 +183,7 @@ struct dg_handle {
   int64_t nscat = 0;
   double t = 0.0;
   int checks = 0;   // numeric monitor interval of dg_solve (0: off)
+  int tile = 0;     // stage kernel family (dg_opts.tile_id, 0 resolved)
 
   bool f64() const { return prec == DG_F64; }
   void* at(size_t off) const { return ws + off; }
@@ -344,6 +347,7 @@ int stage_launch(dg_handle* h, bool stage, const void* in, void* out, double a, 
   args.b = b;
   args.dt = dt;
   args.split_bf16 = h->prec == DG_BF16X3;
+  args.wide_tiles = h->tile == 3;
   if (h->nscat) {
     args.src.rec = static_cast<const double*>(h->at(h->lay.off_src));
     args.src.phase = static_cast<const double*>(h->at(h->lay.off_phase));
@@ -503,6 +507,7 @@ int setup_impl(const dg_mesh* mesh, const dg_opts* opts, const std::vector<int32
   h->nscat = int64_t(h->mesh.scat_face.size());
   if (h->nscat && h->batch) return fail(DG_E_UNSUPPORTED, "scatterer faces are not supported in a batch");
   h->lay = make_layout(h->K, h->N, h->Np, h->Nfp, h->prec, !h->mat.empty(), h->batch, h->nscat, opts->tile_id);
+  h->tile = resolve_tile(h->N, h->prec, opts->tile_id);
   if (h->device >= 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = set_device(h.get());

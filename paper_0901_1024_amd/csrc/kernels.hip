@@ -3062,7 +3062,7 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
     if (N == 7) return launch_variant<7, WmfmaLaunch>(stage, ops, a, s);
   }
   if (!f64 && ops.opfrag) {
-    if (N == 3) return launch_variant<3, SmfmaLaunch>(stage, ops, a, s);
+    if (N == 3) return a.wide_tiles ? launch_mfma_t<3>(stage, ops, a, s) : launch_variant<3, SmfmaLaunch>(stage, ops, a, s);
     if (N == 4) return launch_mfma_t<4>(stage, ops, a, s);
     if (N == 5) return launch_hmfma_t<5>(stage, ops, a, s);
     if (N == 6) return launch_hmfma_t<6>(stage, ops, a, s);

@@ -66,6 +66,7 @@ struct StageArgs {
   double a, b, dt;   // stage coefficients (stage mode only)
   SrcArgs src;       // scattered-field form (src.rec == NULL: none)
   bool split_bf16 = false;   // FP32 state, split-BF16 contraction (operator table in bf16)
+  bool wide_tiles = false;   // FP32 N = 3: the 16-element contraction kernel instead of the 8-element one
 };
 
 // One RHS evaluation (stage == false) or one fused LSRK4 stage (stage == true).

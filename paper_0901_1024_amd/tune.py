@@ -55,6 +55,8 @@ def candidates(order, precision):
         out.append(1)
     if (precision == "f32" and 3 <= order <= 7) or (precision == "f64" and order in (3, 5, 6, 7)):
         out.append(2)
+    if precision == "f32" and order == 3:            # 16-element contraction tiles
+        out.append(3)
     return out
 
 
