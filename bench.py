@@ -552,7 +552,7 @@ def main():
                       else f"mfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N == 4
                       else f"hmfma_stage_kernel<{N},true,{mat},false>" if prec == "f32" and N in (5, 6, 7)
                       else f"dmfma_stage_kernel<{N},true,{mat},false>" if prec == "f64" and N == 3
-                      else f"wmfma_stage_kernel<{N},true,{mat},false>" if prec == "f64" and N in (5, 6, 7)
+                      else f"wmfma_stage_kernel<{N},true,{mat},false>" if prec == "f64" and N in (4, 5, 6, 7)
                       else f"bmfma_stage_kernel<{N},true,{mat},false>" if prec == "bf16x3"
                       else f"stage_kernel<{'float' if prec == 'f32' else 'double'},{N},true>")
     roof["hbm_gbs_algorithmic"] = round(gbs, 1)

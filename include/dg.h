@@ -83,7 +83,7 @@ typedef struct {
   int32_t tile_id;   /* stage kernel: 0 = the library's default (the contraction kernel where
                         the order and precision have one), 1 = element-wise kernel (one thread
                         per element node; not FP32 N = 4, whose rows are padded, nor DG_BF16X3),
-                        2 = contraction kernel (FP32 N = 3..7, FP64 N = 3, 5, 6, 7, DG_BF16X3),
+                        2 = contraction kernel (FP32 and FP64 N = 3..7, DG_BF16X3),
                         3 = contraction kernel with 16-element tiles instead of 8 (FP32 N = 3);
                         DG_E_UNSUPPORTED otherwise. An autotuner picks it per order, precision
                         and mesh size (paper_0901_1024_amd.tune) */

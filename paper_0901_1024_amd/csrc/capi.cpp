@@ -62,7 +62,7 @@ size_t opfrag_bytes_for(int N, int prec, int tile_id = 0) {
   if (resolve_tile(N, prec, tile_id) < 2) return 0;
   if (prec == DG_BF16X3) return size_t(dgk::bopcat_words(N)) * 2;
   const bool used = prec == DG_F32 ? dgk::mfma_order(N) : dgk::dmfma_order(N);
-  return used ? size_t(dgk::opcat_words(N)) * (prec == DG_F64 ? 8 : 4) : 0;
+  return used ? size_t(dgk::opcat_words(N, prec == DG_F64)) * (prec == DG_F64 ? 8 : 4) : 0;
 }
 
 // Nearest bf16 value (round to nearest even) of a double, as a double; its bit pattern is
@@ -274,10 +274,10 @@ int upload(dg_handle* h, hipStream_t s) {
   } else if (h->lay.opcat_bytes) {
     // OpCat = [Dr | Ds | Dt | LIFT] in the lane order of the contraction kernel
     const int Np = h->Np, Nf4 = 4 * h->Nfp;
-    std::vector<double> oc(size_t(dgk::opcat_words(h->N)), 0.0);
+    std::vector<double> oc(size_t(dgk::opcat_words(h->N, h->f64())), 0.0);
     for (size_t w = 0; w < oc.size(); ++w) {
       int n = -1, blk = -1, col = -1;
-      dgk::opfrag_source(h->N, int(w), &n, &blk, &col);
+      dgk::opfrag_source(h->N, h->f64(), int(w), &n, &blk, &col);
       if (n < 0 || blk < 0 || blk > 3 || col < 0) return fail(DG_E_ARG, "internal: bad operator fragment map");
       if (n >= Np) continue;
       if (blk < 3 && col < Np) {

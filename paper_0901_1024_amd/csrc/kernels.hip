@@ -1484,7 +1484,7 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 }
 
 // ---------------------------------------------------------------------------------------
-// MFMA form of the fused stage in FP64 at the high orders (N = 5, 6, 7).
+// MFMA form of the fused stage in FP64 at N = 4..7.
 //
 // The contraction of the FP32 kernel for these orders (8-element tiles, three 16-row tiles
 // owned by every wave, one wave per 16-node column tile, the last one padded; the operator
@@ -1498,21 +1498,32 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 // Exterior traces of the next tile are gathered after the contraction (their registers are not
 // live across it); the residual is loaded after them, for the update. Issue priorities and
 // nontemporal residual and state I/O as in the other contraction kernels. Result layout: lane
-// (li, g4) register i = row 16 t + g4 + 4 i of row tile t, node 16 nt + li.
+// (li, g4) register i = row 16 t + g4 + 4 i of row tile t, node 16 nt + li. At N = 4 (35
+// nodes) the LDS rows are padded to 36 words (the pad word stays zero, so the last volume
+// single reads zero there); the HBM rows stay unpadded, so a 16-byte chunk of the tile may
+// straddle two LDS rows and is moved as two words.
 template <int N>
 struct WDims {
-  using H = HDims<N>;                                 // tile, wave and operator geometry
-  static constexpr int Np = H::Np, Nfp = H::Nfp, Nf4 = H::Nf4, E = H::E, ROWS = H::ROWS;
-  static constexpr int RT = H::RT, NT = H::NT, THREADS = H::THREADS, NPP = H::NPP, NF = H::NF;
-  static constexpr int KS = H::KS, VB = H::VB, VR = H::VR, QV = H::QV, QF = H::QF, NQ = H::NQ;
-  static constexpr int FIT = H::FIT, OPC = H::OPC;
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, Nf4 = Dims<N>::Nf4;
+  static constexpr int E = 8;                         // elements per tile
+  static constexpr int ROWS = 6 * E, RT = ROWS / 16;  // (field, element) rows, field-major
+  static constexpr int NPP = (Np + 3) / 4 * 4;        // LDS row of a field (N = 4: one zero pad word)
+  static constexpr int NT = (NPP + 15) / 16;          // column tiles (last one padded)
+  static constexpr int THREADS = 64 * NT;             // one wave per column tile
+  static constexpr int NF = (Nf4 + 15) / 16 * 16;
+  static constexpr int KV = 3 * NPP, KD = KV + NF, KS = KD / 4;
+  static constexpr int VB = NPP / 16, VR = (NPP - 16 * VB) / 4;
+  static constexpr int QV = 3 * VB, QF = NF / 16, NQ = QV + QF;
+  static constexpr int FIT = (E * Nf4 + THREADS - 1) / THREADS;
+  static constexpr int OPC = NT * KS * 64;            // fragment-ordered operator, no tail
   static constexpr int ES = 6 * NPP + 2;              // element stride in LDS (doubles, = 2 mod 4)
   static constexpr int RSL = NF + 2;                  // flux row stride (doubles, = 2 mod 4)
-  static constexpr int TW = E * 6 * Np;               // doubles per tile
+  static constexpr int TW = E * 6 * Np;               // doubles per tile (HBM rows are unpadded)
   static constexpr int TC = TW / 2;                   // 16-byte chunks per tile
   static constexpr int CPT = (TC + THREADS - 1) / THREADS;
   static constexpr int LA = 3;                        // operator quads in flight per wave
-  static_assert(NPP == Np, "FP64 rows are unpadded");
+  static_assert(4 * NQ + 3 * VR == KS, "k-steps are quads and singles");
+  static_assert((6 * Np) % 2 == 0, "16-byte chunks do not straddle elements");
   static_assert(TW <= ROWS * RSL, "staging fits in the flux rows");
   static_assert(NQ > LA, "the lookahead is shorter than the quad sequence");
 };
@@ -1541,9 +1552,12 @@ __global__ __launch_bounds__(WDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   const int tid = threadIdx.x, lane = tid & 63;
   const int nt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's column tile
   const int g4 = lane >> 4, li = lane & 15;
+  // LDS slot of word q of a tile of the [K][6][Np] arrays (rows padded to NPP in LDS)
   auto slot = [](int q) __attribute__((always_inline)) {
-    const int e = q / (6 * NP);
-    return e * ES + (q - e * 6 * NP);
+    const int e = q / (6 * NP), r = q - e * 6 * NP;
+    if constexpr (NPP == NP) return e * ES + r;
+    const int f = r / NP;
+    return e * ES + f * NPP + (r - f * NP);
   };
 
   const int nwg = gridDim.x / kXcds;
@@ -1622,7 +1636,14 @@ __global__ __launch_bounds__(WDims<N>::THREADS) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int c = tid + r * NTH;
-        if ((r + 1) * NTH <= TC || c < TC) *reinterpret_cast<doublex2*>(up_s + slot(2 * c)) = pu[r];
+        if ((r + 1) * NTH <= TC || c < TC) {
+          if constexpr (NPP == NP) {
+            *reinterpret_cast<doublex2*>(up_s + slot(2 * c)) = pu[r];
+          } else {   // a chunk may straddle two padded rows
+            up_s[slot(2 * c)] = pu[r].x;
+            up_s[slot(2 * c + 1)] = pu[r].y;
+          }
+        }
       }
 #pragma unroll
       for (int r = 0; r < GPT; ++r) {
@@ -1815,7 +1836,12 @@ __global__ __launch_bounds__(WDims<N>::THREADS) __attribute__((amdgpu_waves_per_
         if ((r + 1) * NTH <= TC || c < TC) {
           const doublex2 h = reinterpret_cast<const doublex2*>(stage)[c];
           if (STAGE) {
-            const doublex2 u = *reinterpret_cast<const doublex2*>(up_s + slot(2 * c));
+            doublex2 u;
+            if constexpr (NPP == NP) {
+              u = *reinterpret_cast<const doublex2*>(up_s + slot(2 * c));
+            } else {
+              u = doublex2{up_s[slot(2 * c)], up_s[slot(2 * c + 1)]};
+            }
             const doublex2 rv = doublex2{ca * rs[r].x + cdt * h.x, ca * rs[r].y + cdt * h.y};
             __builtin_nontemporal_store(rv, r2 + c);
             __builtin_nontemporal_store(doublex2{u.x + cb * rv.x, u.y + cb * rv.y}, o2 + c);
@@ -2924,7 +2950,8 @@ int grid_for(int64_t total) {
 
 }  // namespace
 
-int opcat_words(int N) {
+int opcat_words(int N, bool f64) {
+  if (f64 && N == 4) return WDims<4>::OPC;   // FP64 N = 4: three padded column tiles, no tail
   switch (N) {
     case 3: return MDims<3>::OPC;
     case 4: return MDims<4>::OPC;
@@ -2937,7 +2964,7 @@ int opcat_words(int N) {
 
 bool mfma_order(int N) { return contraction_order(N); }
 
-bool dmfma_order(int N) { return N == 3 || (N >= 5 && N <= 7); }
+bool dmfma_order(int N) { return N >= 3 && N <= 7; }
 
 bool bf16x3_order(int N) { return N >= 5 && N <= 7; }
 
@@ -3036,7 +3063,8 @@ void opfrag_source_t(int w, int* n, int* blk, int* col) {
 }
 }  // namespace
 
-void opfrag_source(int N, int w, int* n, int* blk, int* col) {
+void opfrag_source(int N, bool f64, int w, int* n, int* blk, int* col) {
+  if (f64 && N == 4) return opfrag_source_t<WDims<4>>(w, n, blk, col);
   switch (N) {
     case 3: return opfrag_source_t<MDims<3>>(w, n, blk, col);
     case 4: return opfrag_source_t<MDims<4>>(w, n, blk, col);
@@ -3057,6 +3085,7 @@ hipError_t launch_stage(int N, bool f64, bool stage, const OpsView& ops, const S
   }
   if (f64 && ops.opfrag) {
     if (N == 3) return launch_variant<3, DmfmaLaunch>(stage, ops, a, s);
+    if (N == 4) return launch_variant<4, WmfmaLaunch>(stage, ops, a, s);
     if (N == 5) return launch_variant<5, WmfmaLaunch>(stage, ops, a, s);
     if (N == 6) return launch_variant<6, WmfmaLaunch>(stage, ops, a, s);
     if (N == 7) return launch_variant<7, WmfmaLaunch>(stage, ops, a, s);

@@ -22,12 +22,14 @@ struct OpsView {
   const void* opfrag;
 };
 
-// Floats in the fragment-ordered operator for order N (0 when no contraction kernel serves N).
-int opcat_words(int N);
+// Words in the fragment-ordered operator for order N in the given precision (0 when no
+// contraction kernel serves N). The layouts of the two precisions agree except at N = 4, where
+// the FP32 kernel has two column tiles and a 4-column tail and the FP64 one three column tiles.
+int opcat_words(int N, bool f64);
 // Whether the FP32 MFMA stage kernel serves order N.
 bool mfma_order(int N);
-// Whether an FP64 MFMA stage kernel serves order N (N = 3, 5, 6, 7; each reads the operator
-// table of the FP32 kernel of the same order, in FP64).
+// Whether an FP64 MFMA stage kernel serves order N (N = 3..7; each reads the operator table of
+// the FP32 kernel of the same order in FP64, except at N = 4: see opcat_words).
 bool dmfma_order(int N);
 // Whether the split-BF16 contraction kernel serves order N.
 bool bf16x3_order(int N);
@@ -40,10 +42,11 @@ void bopfrag_source(int N, int w, int* n, int* blk, int* col, int* part);
 // Words per (element, field) row of the internal field arrays, [K][6][S]: Np, rounded up to a
 // multiple of 4 for the FP32 contraction orders (the pad words are kept zero).
 int row_stride(int N, bool f64);
-// Word w of the fragment-ordered operator of order N holds row n of operator block blk
-// (0, 1, 2 = Dr, Ds, Dt; 3 = LIFT) at column col; it is zero when n, col fall outside the
-// operator (n >= Np, col >= Np for a D block, col >= 4 Nfp for LIFT).
-void opfrag_source(int N, int w, int* n, int* blk, int* col);
+// Word w of the fragment-ordered operator of order N (in the layout of the given precision)
+// holds row n of operator block blk (0, 1, 2 = Dr, Ds, Dt; 3 = LIFT) at column col; it is zero
+// when n, col fall outside the operator (n >= Np, col >= Np for a D block, col >= 4 Nfp for
+// LIFT).
+void opfrag_source(int N, bool f64, int w, int* n, int* blk, int* col);
 
 // Incident field of the scattered-field form (read on scatterer faces only).
 struct SrcArgs {

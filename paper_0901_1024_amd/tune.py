@@ -53,7 +53,7 @@ def candidates(order, precision):
     out = []
     if not (precision == "f32" and order == 4):      # FP32 N = 4 rows are padded for the matrix cores
         out.append(1)
-    if (precision == "f32" and 3 <= order <= 7) or (precision == "f64" and order in (3, 5, 6, 7)):
+    if (precision == "f32" and 3 <= order <= 7) or (precision == "f64" and 3 <= order <= 7):
         out.append(2)
     if precision == "f32" and order == 3:            # 16-element contraction tiles
         out.append(3)

@@ -205,7 +205,7 @@ def test_kernel_choice_is_checked_on_the_host():
     P.Solver(v, e, 3, "f64", device=-1, tile_id=2)
     P.Solver(v, e, 5, "f64", device=-1, tile_id=2)
     P.Solver(v, e, 3, "f32", device=-1, tile_id=3)
-    for N, prec, tid in [(4, "f32", 1), (4, "f64", 2), (2, "f32", 2), (5, "bf16x3", 1), (4, "f32", 3),
+    for N, prec, tid in [(4, "f32", 1), (2, "f64", 2), (8, "f64", 2), (2, "f32", 2), (5, "bf16x3", 1), (4, "f32", 3),
                          (3, "f64", 3), (3, "f32", 4)]:
         with pytest.raises(P.DGError):
             P.Solver(v, e, N, prec, device=-1, tile_id=tid)

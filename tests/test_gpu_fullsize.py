@@ -84,12 +84,12 @@ def test_fp32_full_size_steady_state_loop(N, n, medium):
 
 
 @pytest.mark.parametrize("medium", [False, True])
-@pytest.mark.parametrize("N,n", [(3, 39), (5, 31), (7, 25)])
+@pytest.mark.parametrize("N,n", [(3, 39), (4, 31), (5, 31), (7, 25)])
 def test_fp64_contraction_kernel_full_size(N, n, medium):
     """FP64 on its contraction kernels at full size, 8-element tiles with a ragged last one:
-    N = 3 on 355,914 = 8 * 44,489 + 2 elements, N = 5 on 178,746 = 8 * 22,343 + 2, N = 7 on
-    93,750 = 8 * 11,718 + 6 (every workgroup takes many tiles); vacuum and medium with
-    absorbing faces."""
+    N = 3 on 355,914 = 8 * 44,489 + 2 elements, N = 4 (padded LDS rows) and N = 5 on 178,746 =
+    8 * 22,343 + 2, N = 7 on 93,750 = 8 * 11,718 + 6 (every workgroup takes many tiles);
+    vacuum and medium with absorbing faces."""
     v, e, m, u, eps, mu, fb, absorb = big_problem(N, n)
     say(f"case: N={N} K={m.K} f64 full size, shuffled vertices, {'medium+absorbing' if medium else 'vacuum'}")
     kw = dict(eps=eps, mu=mu, absorb=absorb) if medium else {}

@@ -17,8 +17,8 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
-@pytest.mark.parametrize("prec,N", [("f32", 3), ("f32", 5), ("f32", 6), ("f32", 7), ("f64", 3), ("f64", 5),
-                                    ("f64", 6), ("f64", 7)])
+@pytest.mark.parametrize("prec,N", [("f32", 3), ("f32", 5), ("f32", 6), ("f32", 7), ("f64", 3), ("f64", 4),
+                                    ("f64", 5), ("f64", 6), ("f64", 7)])
 def test_both_kernel_families_match_oracle(prec, N):
     v, e = dginputs.kuhn_cube(3, jitter=0.15, permute=True, shuffle=True)
     m = Mm.Mesh(v, e, R.ref_element(N))
