@@ -5,9 +5,10 @@ generative approach; Sec. 6, the method-parameter table). Here the search space 
 family of each order and precision: the element-wise kernel (one thread per element node, as
 many workgroups as tiles of 256 / Np elements) against the contraction kernel (16- or
 8-element tiles on the matrix cores, a persistent grid), which differ most on small meshes
-that do not fill the device. tune() times both on synthetic meshes of each size bucket
+that do not fill the device, and at FP32 N = 3 also the tile shape of the contraction kernel
+(8 or 16 elements). tune() times the candidates on synthetic meshes of each size bucket
 (jittered, permuted Kuhn cubes, smooth fields; a number of graph-replayed steps after a warm-up)
-and stores the faster per (precision, order, size) in a JSON table; choose() reads the table
+and stores the fastest per (precision, order, size) in a JSON table; choose() reads the table
 (the nearest bucket in log size) for Solver(..., tile_id="auto").
 """
 from __future__ import annotations
