@@ -76,6 +76,26 @@ def recorded_traffic(N, prec, K):
     return float(rec["traffic_bytes_per_launch"])
 
 
+def device_copy_gbs(torch, nbytes=1 << 30, reps=10):
+    """Bytes moved (read + write) per second by torch's device-to-device copy of nbytes."""
+    import numpy as np
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        t.append(e0.elapsed_time(e1) / 1e3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / float(np.median(t)) / 1e9
+
+
 def rhs_flops_per_elem(N):
     """Algorithmic flops of one right-hand side per element (the fused stage without the
     30 Np of the RK update)."""
@@ -560,6 +580,11 @@ def main():
     roof["tflops_algorithmic"] = round(tflops_k, 2)
     roof["us_per_launch"] = round(per_launch_s * 1e6, 2)
     roof["dg_rhs_us"] = round(float(np.median(rhs_us)), 2)
+    # attainable HBM bandwidth on this machine: a plain 1 GiB device-to-device copy (read + write),
+    # median of 10, beside the nominal 8 TB/s
+    copy_gbs = device_copy_gbs(torch)
+    roof["copy_gbs_measured"] = round(copy_gbs, 1)
+    roof["hbm_frac_of_copy"] = round(gbs / copy_gbs, 4)
     if len(reps_us):
         roof["launch_us_reps"] = {"median": round(float(np.median(reps_us)), 2),
                                   "p10": round(float(np.percentile(reps_us, 10)), 2),
