@@ -580,7 +580,7 @@ def main():
     roof["tflops_algorithmic"] = round(tflops_k, 2)
     roof["us_per_launch"] = round(per_launch_s * 1e6, 2)
     roof["dg_rhs_us"] = round(float(np.median(rhs_us)), 2)
-    # attainable HBM bandwidth on this machine: a plain 1 GiB device-to-device copy (read + write),
+    # attainable HBM bandwidth on this GPU: a plain 1 GiB device-to-device copy (read + write),
     # median of 10, beside the nominal 8 TB/s
     copy_gbs = device_copy_gbs(torch)
     roof["copy_gbs_measured"] = round(copy_gbs, 1)
