@@ -456,7 +456,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU domain decomposition is a design, not part of this build)",
+              "(the library runs one GPU per process; a multi-GPU domain decomposition is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
