@@ -103,11 +103,12 @@ def test_bf16x3_within_derived_bound(N, medium):
     s32.free()
 
 
-def test_bf16x3_full_size_steady_state_loop():
-    """N = 5 on 6 * 31^3 = 178,746 shuffled tets (8-element tiles, a ragged last one, many
-    tiles per persistent workgroup): sampled right-hand side within the bound."""
-    N = 5
-    v, e = dginputs.kuhn_cube(31, jitter=0.15, permute=True, shuffle=True)
+@pytest.mark.parametrize("N,n", [(5, 31), (7, 25)])
+def test_bf16x3_full_size_steady_state_loop(N, n):
+    """N = 5 on 6 * 31^3 = 178,746 and N = 7 on 6 * 25^3 = 93,750 shuffled tets (8-element
+    tiles, a ragged last one, many tiles per persistent workgroup): sampled right-hand side
+    within the bound."""
+    v, e = dginputs.kuhn_cube(n, jitter=0.15, permute=True, shuffle=True)
     m = Mm.Mesh(v, e, R.ref_element(N), compute_maps=False)
     u = rounded(dginputs.eval_smooth_fields(dginputs.smooth_field_modes(), *m.x), "f32")
     say(f"case: bf16x3 N={N} K={m.K} full size")

@@ -65,9 +65,10 @@ def check_sampled(s, m, u, kw, prec, nsample, nstep, seed):
 
 
 # (order, cube size n): K = 6 n^3 leaves a ragged last tile (16-element tiles at N = 4:
-# 355,914 = 16 * 22,244 + 10; 8-element tiles at N = 3, 5, 6: 355,914 = 8 * 44,489 + 2 and
-# 178,746 = 8 * 22,343 + 2), and every workgroup of the persistent grid takes many tiles
-FULL = [(3, 39), (4, 39), (5, 31), (6, 31)]
+# 355,914 = 16 * 22,244 + 10; 8-element tiles at N = 3, 5, 6, 7: 355,914 = 8 * 44,489 + 2,
+# 178,746 = 8 * 22,343 + 2 and 93,750 = 8 * 11,718 + 6), and every workgroup of the
+# persistent grid takes many tiles (at N = 7 the operator strip is streamed per tile)
+FULL = [(3, 39), (4, 39), (5, 31), (6, 31), (7, 25)]
 
 
 @pytest.mark.parametrize("medium", [False, True])   # innermost: both variants share a mesh
@@ -84,10 +85,10 @@ def test_fp32_full_size_steady_state_loop(N, n, medium):
 
 
 @pytest.mark.parametrize("medium", [False, True])
-@pytest.mark.parametrize("N,n", [(3, 39), (4, 31), (5, 31), (7, 25)])
+@pytest.mark.parametrize("N,n", [(3, 39), (4, 31), (5, 31), (6, 31), (7, 25)])
 def test_fp64_contraction_kernel_full_size(N, n, medium):
     """FP64 on its contraction kernels at full size, 8-element tiles with a ragged last one:
-    N = 3 on 355,914 = 8 * 44,489 + 2 elements, N = 4 (padded LDS rows) and N = 5 on 178,746 =
+    N = 3 on 355,914 = 8 * 44,489 + 2 elements, N = 4 (padded LDS rows), 5 and 6 on 178,746 =
     8 * 22,343 + 2, N = 7 on 93,750 = 8 * 11,718 + 6 (every workgroup takes many tiles);
     vacuum and medium with absorbing faces."""
     v, e, m, u, eps, mu, fb, absorb = big_problem(N, n)
