@@ -180,12 +180,13 @@ def _stream_ptr(stream):
 
 
 class Solver:
-    """One mesh, one order, one precision: a handle of libdg.
+    """One mesh, one order (1..9), one precision ("f64", "f32", "bf16x3"): a handle of libdg.
 
     device >= 0: the workspace is a torch uint8 tensor on cuda:device (PyTorch owns the HBM);
     device = -1: host-only handle (builder outputs only).
     face_bc: (K, 4) int8, 0 automatic, 1 wall, 2 absorbing, 3 scatterer; eps, mu: (K,) per
-    element; checks: numeric monitor interval of solve() in steps (0 = off).
+    element; checks: numeric monitor interval of solve() in steps (0 = off); tile_id: stage
+    kernel choice (see _tile_option).
     """
 
     def __init__(self, vxyz, etov, order, precision="f64", reorder=1, device=0, face_bc=None,
