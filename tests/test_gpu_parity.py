@@ -174,7 +174,7 @@ def test_solve_equals_repeated_steps_and_field_round_trip():
     assert np.array_equal(a, s.get_fields())
 
 
-@pytest.mark.parametrize("N", [1, 3, 5, 7])
+@pytest.mark.parametrize("N", [1, 3, 4, 5, 6, 7, 9])
 def test_degenerate_meshes_single_and_two_tets(N):
     one_v = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
     two_v = np.vstack([one_v, [[0.9, 0.8, 0.95]]])
@@ -211,11 +211,12 @@ def test_fp32_field_round_trip_and_energy(N):
         s.free()
 
 
-@pytest.mark.parametrize("N", [3, 4, 5, 6])
+@pytest.mark.parametrize("N", [3, 4, 5, 6, 7])
 def test_fp32_meshes_smaller_than_a_tile(N):
     """The FP32 contraction kernels on 1, 2 and 6 elements (one ragged tile, shorter than a
     tile of the field arrays, so every clamped prefetch index lands inside the arrays): the
-    right-hand side and one RK step against the oracle, in vacuum and in a medium."""
+    right-hand side and one RK step against the oracle, in vacuum and in a medium (N = 7: the
+    streamed operator strip)."""
     one_v = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
     two_v = np.vstack([one_v, [[0.9, 0.8, 0.95]]])
     cube_v, cube_e = dginputs.kuhn_cube(1, jitter=0.1, permute=True)
