@@ -34,13 +34,14 @@ class Request:
     face_bc: Optional[np.ndarray] = None
     eps: Optional[np.ndarray] = None
     mu: Optional[np.ndarray] = None
+    deadline: Optional[float] = None  # seconds after arrival; a solve not done by then is cancelled
     # filled in by the server
     footprint: int = 0
     t_admit: Optional[float] = None
     t_start: Optional[float] = None
     t_done: Optional[float] = None
     result: Optional[np.ndarray] = None
-    error: Optional[str] = None       # set when the numeric monitor stopped the solve
+    error: Optional[str] = None       # set when the numeric monitor stopped the solve or it was cancelled
 
     @property
     def latency(self) -> float:
@@ -93,7 +94,9 @@ class Server:
     captured two-step graph); keep_results: copy each final state to the host; checks: after
     every chunk, a solve whose energy is not finite or has grown (more than check_tol relative
     to its energy at admission) is stopped and reported with `error`, and its memory freed; the
-    other solves are not affected."""
+    other solves are not affected. cancel(rid), from any thread while run() is going, or a
+    request's deadline, stops a request: a waiting one leaves the queue, a running one is
+    released once its current chunk has finished; it is reported with `error` and no result."""
 
     def __init__(self, budget_bytes: int, slots: int = 4, chunk_steps: int = 64, device: int = 0,
                  keep_results: bool = False, setup_threads: int = 4, backend=None, checks: bool = False,
@@ -110,6 +113,21 @@ class Server:
         self.checks = checks
         self.check_tol = check_tol
         self.backfill = backfill
+        self._cancel_lock = threading.Lock()
+        self._cancelled = set()
+
+    def cancel(self, rid):
+        """Ask run() to stop request rid (thread-safe; a no-op for finished requests)."""
+        with self._cancel_lock:
+            self._cancelled.add(rid)
+
+    def _stop_wanted(self, r, now):
+        if r.deadline is not None and now - r.arrival > r.deadline:
+            return f"cancelled: deadline of {r.deadline} s passed"
+        with self._cancel_lock:
+            if r.rid in self._cancelled:
+                return "cancelled"
+        return None
 
     def run(self, requests, clock=time.perf_counter, idle_sleep=2e-4):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -124,6 +142,13 @@ class Server:
         with ThreadPoolExecutor(max_workers=self.setup_threads) as pool:
             while pending or setting_up or active:
                 now = clock() - t0
+                # cancelled or overdue requests leave the queue before admission
+                for r in [r for r in pending if r.arrival <= now]:
+                    why = self._stop_wanted(r, now)
+                    if why:
+                        pending.remove(r)
+                        r.error, r.t_done = why, now
+                        done.append(r)
                 # admit while a slot and memory are free: the oldest waiting request first;
                 # with the backfill policy a slot beyond the first goes to the arrived request
                 # of least work instead
@@ -151,6 +176,16 @@ class Server:
                         progressed = True
                 for a in list(active):
                     if a.event is not None and not self.backend.finished(a.event):
+                        continue
+                    why = self._stop_wanted(a.req, clock() - t0) if a.left > 0 else None
+                    if why:   # the stream is idle here: release the solve
+                        a.req.error = why
+                        a.req.t_done = clock() - t0
+                        self.backend.release(a.solver)
+                        used -= a.req.footprint
+                        active.remove(a)
+                        done.append(a.req)
+                        progressed = True
                         continue
                     if self.checks:
                         # the stream is idle here (its last chunk has finished)

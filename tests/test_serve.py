@@ -112,3 +112,36 @@ def test_backfill_admits_oldest_first_then_smallest():
         _requests([50, 40, 5], [0.0, 0.0, 0.0], steps=4))
     pb = {r.rid: r for r in plain}
     assert pb[1].t_admit <= pb[2].t_admit                        # arrival order without backfill
+
+
+def test_cancel_and_deadline_stop_only_their_requests():
+    # a counting clock: one unit per reading, so deadlines are deterministic
+    ticks = iter(range(10 ** 9))
+
+    def clock():
+        return float(next(ticks))
+
+    class CancellingBackend(FakeBackend):
+        """Cancels request 1 from inside its first chunk (as another thread would)."""
+        server = None
+
+        def advance(self, solver, stream, dt, n):
+            if solver[0].rid == 1:
+                self.server.cancel(1)
+            return super().advance(solver, stream, dt, n)
+
+    be = CancellingBackend()
+    reqs = _requests([10, 20, 30, 40], [0.0] * 4, steps=8)
+    reqs[2].deadline = 0.0                       # overdue on arrival: never admitted
+    reqs[3].deadline = 1e9
+    srv = Server(budget_bytes=10 ** 6, slots=2, chunk_steps=2, backend=be)
+    be.server = srv
+    done = srv.run(reqs, clock=clock)
+    by = {r.rid: r for r in done}
+    assert len(done) == 4
+    assert by[1].error == "cancelled" and by[1].result is None and by[1].t_admit is not None
+    assert by[2].error and "deadline" in by[2].error and by[2].t_admit is None
+    assert by[0].error is None and by[3].error is None
+    assert be.in_flight == 0 and be.used == 0            # the cancelled solve was released
+    s = summary(done)
+    assert s["completed"] == 2 and s["failed"] == 2
