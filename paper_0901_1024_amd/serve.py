@@ -117,7 +117,9 @@ class Server:
         self._cancelled = set()
 
     def cancel(self, rid):
-        """Ask run() to stop request rid (thread-safe; a no-op for finished requests)."""
+        """Ask run() to stop request rid (thread-safe; a no-op for finished requests). A
+        cancellation holds for the run that is going: when run() returns it forgets the ids of
+        the requests it was given, so a later run may reuse them."""
         with self._cancel_lock:
             self._cancelled.add(rid)
 
@@ -218,6 +220,8 @@ class Server:
                     progressed = True
                 if not progressed:
                     time.sleep(idle_sleep)
+        with self._cancel_lock:
+            self._cancelled.difference_update(r.rid for r in done)
         return done
 
 

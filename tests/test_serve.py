@@ -145,3 +145,24 @@ def test_cancel_and_deadline_stop_only_their_requests():
     assert be.in_flight == 0 and be.used == 0            # the cancelled solve was released
     s = summary(done)
     assert s["completed"] == 2 and s["failed"] == 2
+
+
+def test_a_cancellation_does_not_outlive_its_run():
+    """Ids cancelled during a run (here each one just after its request finished) are
+    forgotten when the run returns: a later run on the same server that reuses the ids
+    completes every request."""
+
+    class LateCancel(FakeBackend):
+        server = None
+
+        def release(self, solver):
+            super().release(solver)
+            self.server.cancel(solver[0].rid)     # a cancel that arrives after the finish
+
+    be = LateCancel()
+    srv = Server(budget_bytes=10 ** 6, slots=2, chunk_steps=2, backend=be)
+    be.server = srv
+    for _ in range(2):
+        done = srv.run(_requests([10, 20, 30], [0.0] * 3))
+        assert len(done) == 3 and all(r.error is None for r in done)
+    assert be.in_flight == 0 and be.used == 0
