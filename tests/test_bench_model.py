@@ -37,3 +37,41 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _traffic_file(dirpath, sha, value=1.5e9):
+    prof = os.path.join(dirpath, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    with open(os.path.join(prof, "stage_f32_n4_k384000_traffic.txt"), "w") as fh:
+        fh.write("# HBM traffic of one launch\nkernel: mfma_stage_kernel<4, true, false, false>\n"
+                 f"kernel_source_sha256: {sha}\ntraffic_bytes_per_launch: {value}\n")
+
+
+def test_recorded_traffic_is_dropped_once_the_kernel_source_changes(tmp_path, monkeypatch):
+    """The traffic of a committed counter summary is reported only for the kernel source it was
+    measured on (its SHA-256); after any change to that source the bench line says null."""
+    import hashlib
+    src = tmp_path / "kernels.hip"
+    src.write_bytes(b"// kernel source as profiled\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    _traffic_file(str(tmp_path), hashlib.sha256(src.read_bytes()).hexdigest())
+    assert bench.recorded_traffic(4, "f32", 384000) == 1.5e9
+    src.write_bytes(b"// kernel source as profiled, then edited\n")
+    assert bench.recorded_traffic(4, "f32", 384000) is None
+    assert bench.recorded_traffic(5, "f32", 196608) is None        # no summary for that workload
+
+
+def test_committed_traffic_summaries_name_their_source_and_bytes():
+    prof = os.path.join(ROOT, "profiles")
+    names = [n for n in os.listdir(prof) if n.endswith("_traffic.txt")]
+    assert names
+    for n in names:
+        rec = {}
+        with open(os.path.join(prof, n)) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    rec[k.strip()] = v.strip()
+        assert len(rec.get("kernel_source_sha256", "")) == 64, n
+        assert float(rec["traffic_bytes_per_launch"]) > 0, n
