@@ -291,6 +291,15 @@ struct MDims {
 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned uint4v __attribute__((ext_vector_type(4)));
+constexpr int kNonTemporal = 2;   // cache policy of a buffer access: nontemporal
+
+// Resource for raw buffer accesses to the nbytes at base (word 3 in the gfx9 layout: 32-bit data
+// format). A lane whose byte offset lies at or past nbytes is not stored (range check), so a
+// store can be issued by every lane with no condition.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(void* base, int nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, nbytes, 0x00020000);
+}
 
 // MAT: heterogeneous medium. 1/eps and 1/mu of the tile's elements ride in the unused last
 // words of each element row of the padded tile (up_s) and scale the operand coefficients;
@@ -373,8 +382,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<
   float nup[FIT][6];   // exterior traces u+ of the face nodes tq + r kThreads (all six fields)
   int32_t pf = 0;
   float pm = 0.f, pw = 0.f;   // MAT: 1/eps (even threads) or 1/mu (odd threads) of element tid / 2
-  // Every thread loads every slot, on every path, its index clamped into its array (a ragged
-  // or missing next tile loads values that are not used): an exec-masked load makes the
+  // Every thread loads every slot, on every path, its index clamped into its array (a missing
+  // next tile, and the part of a ragged one past the end of the arrays, loads values that are
+  // not used; below the end the clamped index is the right one): an exec-masked load makes the
   // compiler wait for all outstanding loads before reusing its registers, and a load skipped
   // on some path makes a later wait for one load fall back to waiting for all of them.
   const size_t fc_last = size_t(K) * 4 - 1;
@@ -422,6 +432,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<
   gather(tile, fcb[0], 0, FIT);
   prefetch(tile);
   pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+  // The first tile's loads complete here, once per workgroup: nothing issued before the loop is
+  // then pending at its head, and the compiler counts each wait inside the loop from the loop's
+  // own order of issue (loads, then the write-out stores) instead of the prologue's.
+  __builtin_amdgcn_s_waitcnt(0);
 
   for (; tile < tend; tile += nwg) {
     const int base = tile * E;
@@ -451,14 +465,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<
       if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
       if (MAT && tid < 16 * E) wmat[tid] = pw;
     } else {
-      for (int q = tid; q < nel * 6 * NPP; q += kThreads) up_s[slot(q)] = u_in[tb + q];
-      if (MAT) {
-        for (int q = tid; q < 2 * nel; q += kThreads)
-          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
-        for (int q = tid; q < 16 * nel; q += kThreads)
-          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      // a ragged tile comes from the prefetch registers too: the clamped loads read the right
+      // words below the end of the arrays (no load on this path)
+      const int nc = nel * 6 * NPP / 4;
+#pragma unroll
+      for (int j = 0; j < CPC; ++j) {
+        const int c = tz + j * kThreads;
+        if (c < nc) *reinterpret_cast<floatx4*>(up_s + slot(4 * c)) = pu[j];
       }
-      for (int q = tid; q < nel * G; q += kThreads) gt[q] = geo[size_t(base) * G + q];
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * kThreads;
+        if (q < nel * G) gt[q] = pg[r];
+      }
+      if (MAT && tid < 2 * nel) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * nel) wmat[tid] = pw;
     }
     __syncthreads();
 
@@ -509,7 +530,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<
     __syncthreads();
     if (STAGE) {
 #pragma unroll
-      for (int j = 0; j < CPC; ++j)   // clamped like the prefetch (a ragged tile reads res directly)
+      for (int j = 0; j < CPC; ++j)   // clamped like the prefetch (right below the end of the array)
         rs[j] = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(res) +
                                            min(size_t(tile) * TC + min(tid + j * kThreads, TC - 1), chunk_last));
     }
@@ -672,40 +693,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MDims<
     }
     __syncthreads();
 
-    // ---- update and write out, coalesced
-    if (full) {
+    // ---- update and write out, coalesced. Buffer stores bounded by the tile's words, issued by
+    // every lane: a chunk past the tile (the partial last round, a ragged tile) is dropped by the
+    // range check, so no store sits on a conditional path (the compiler's wait counting would
+    // then make the next flux phase wait for these stores to complete).
+    {
+      const int nbytes = nel * 6 * NPP * 4;
+      const __amdgpu_buffer_rsrc_t ro = tile_rsrc(out + tb, nbytes);
+      const __amdgpu_buffer_rsrc_t rr = tile_rsrc(res + tb, nbytes);
       int tw = tid;   // opaque, like tz
       asm volatile("" : "+v"(tw));
 #pragma unroll
       for (int j = 0; j < CPC; ++j) {
         const int c = tw + j * kThreads;
-        if ((j + 1) * kThreads <= TC || c < TC) {
-          const int o = slot(4 * c);
-          const floatx4 h = *reinterpret_cast<const floatx4*>(stage + o);
-          if (STAGE) {
-            const floatx4 u = *reinterpret_cast<const floatx4*>(up_s + o);
-            const floatx4 rv = pad_zero(c, floatx4{ca * rs[j].x + cdt * h.x, ca * rs[j].y + cdt * h.y,
-                                                   ca * rs[j].z + cdt * h.z, ca * rs[j].w + cdt * h.w});
-            // residual and state are touched once per stage: nontemporal, they leave L2 to the
-            // neighbour traces (about 1 % at N = 4)
-            __builtin_nontemporal_store(rv, reinterpret_cast<floatx4*>(res + tb) + c);
-            __builtin_nontemporal_store(floatx4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w},
-                                        reinterpret_cast<floatx4*>(out + tb) + c);
-          } else {
-            reinterpret_cast<floatx4*>(out + tb)[c] = pad_zero(c, h);
-          }
-        }
-      }
-    } else {
-      for (int q = tid; q < nel * 6 * NPP; q += kThreads) {
-        const bool node = q % NPP < NP;   // pad words stay zero
-        const float h = node ? stage[slot(q)] : 0.f;
+        const int o = slot(4 * min(c, TC - 1));
+        const floatx4 h = *reinterpret_cast<const floatx4*>(stage + o);
         if (STAGE) {
-          const float rv = node ? ca * res[tb + q] + cdt * h : 0.f;
-          res[tb + q] = rv;
-          out[tb + q] = up_s[slot(q)] + cb * rv;
+          const floatx4 u = *reinterpret_cast<const floatx4*>(up_s + o);
+          const floatx4 rv = pad_zero(c, floatx4{ca * rs[j].x + cdt * h.x, ca * rs[j].y + cdt * h.y,
+                                                 ca * rs[j].z + cdt * h.z, ca * rs[j].w + cdt * h.w});
+          const floatx4 un = floatx4{u.x + cb * rv.x, u.y + cb * rv.y, u.z + cb * rv.z, u.w + cb * rv.w};
+          // residual and state are touched once per stage: nontemporal, they leave L2 to the
+          // neighbour traces
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, rv), rr, c * 16, 0, kNonTemporal);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, un), ro, c * 16, 0, kNonTemporal);
         } else {
-          out[tb + q] = h;
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, pad_zero(c, h)), ro, c * 16, 0, 0);
         }
       }
     }
@@ -1269,6 +1282,9 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
   gather(tile, fcb[0]);
   prefetch(tile);
   pf = fcode[min(size_t(tile + 2 * nwg) * E * 4 + min(tid, E * 4 - 1), fc_last)];
+  // the first tile's loads complete here, once per workgroup, so that the waits inside the loop
+  // are counted from the loop's own order of issue
+  __builtin_amdgcn_s_waitcnt(0);
 
   for (; tile < tend; tile += nwg) {
     const int base = tile * E;
@@ -1293,14 +1309,21 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
       if (MAT && tid < 2 * E) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
       if (MAT && tid < 16 * E) wmat[tid] = pw;
     } else {
-      for (int q = tid; q < nel * 6 * NPP; q += NTH) up_s[slot(q)] = u_in[tb + q];
-      if (MAT) {
-        for (int q = tid; q < 2 * nel; q += NTH)
-          up_s[(q >> 1) * ES + 6 * NPP + (q & 1)] = mat[(size_t(base) + (q >> 1)) * dgh::kMatStride + (q & 1)];
-        for (int q = tid; q < 16 * nel; q += NTH)
-          wmat[q] = mat[(size_t(base) + q / 16) * dgh::kMatStride + dgh::kMatFace + (q & 15)];
+      // a ragged tile comes from the prefetch registers too: the clamped loads read the right
+      // words below the end of the arrays (no load on this path)
+      const int nc = nel * 6 * NPP / 2;
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int c = tid + r * NTH;
+        if (c < nc) *reinterpret_cast<doublex2*>(up_s + slot(2 * c)) = pu[r];
       }
-      for (int q = tid; q < nel * G; q += NTH) gt[q] = geo[size_t(base) * G + q];
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = tid + r * NTH;
+        if (q < nel * G) gt[q] = pg[r];
+      }
+      if (MAT && tid < 2 * nel) up_s[(tid >> 1) * ES + 6 * NPP + (tid & 1)] = pm;
+      if (MAT && tid < 16 * nel) wmat[tid] = pw;
     }
     __syncthreads();
 
@@ -1445,35 +1468,26 @@ __global__ __launch_bounds__(DDims<N>::THREADS) __attribute__((amdgpu_waves_per_
     }
     __syncthreads();
 
-    // ---- update and write out, 16-byte chunks
-    if (full) {
-      doublex2* o2 = reinterpret_cast<doublex2*>(out + tb);
-      doublex2* r2 = reinterpret_cast<doublex2*>(res + tb);
+    // ---- update and write out, 16-byte chunks: buffer stores bounded by the tile's words, issued
+    // by every lane (a chunk past the tile is dropped by the range check; no store on a
+    // conditional path, so the next flux phase does not wait for these stores)
+    {
+      const int nbytes = nel * 6 * NPP * 8;
+      const __amdgpu_buffer_rsrc_t ro = tile_rsrc(out + tb, nbytes);
+      const __amdgpu_buffer_rsrc_t rr = tile_rsrc(res + tb, nbytes);
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         const int c = tid + r * NTH;
-        if ((r + 1) * NTH <= TC || c < TC) {
-          const int o = slot(2 * c);
-          const doublex2 h = *reinterpret_cast<const doublex2*>(stage + o);
-          if (STAGE) {
-            const doublex2 u = *reinterpret_cast<const doublex2*>(up_s + o);
-            const doublex2 rv = doublex2{ca * rs[r].x + cdt * h.x, ca * rs[r].y + cdt * h.y};
-            __builtin_nontemporal_store(rv, r2 + c);
-            __builtin_nontemporal_store(doublex2{u.x + cb * rv.x, u.y + cb * rv.y}, o2 + c);
-          } else {
-            o2[c] = h;
-          }
-        }
-      }
-    } else {
-      for (int q = tid; q < nel * 6 * NPP; q += NTH) {
-        const double h = stage[slot(q)];
+        const int o = slot(2 * min(c, TC - 1));
+        const doublex2 h = *reinterpret_cast<const doublex2*>(stage + o);
         if (STAGE) {
-          const double rv = ca * res[tb + q] + cdt * h;
-          res[tb + q] = rv;
-          out[tb + q] = up_s[slot(q)] + cb * rv;
+          const doublex2 u = *reinterpret_cast<const doublex2*>(up_s + o);
+          const doublex2 rv = doublex2{ca * rs[r].x + cdt * h.x, ca * rs[r].y + cdt * h.y};
+          const doublex2 un = doublex2{u.x + cb * rv.x, u.y + cb * rv.y};
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, rv), rr, c * 16, 0, kNonTemporal);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, un), ro, c * 16, 0, kNonTemporal);
         } else {
-          out[tb + q] = h;
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, h), ro, c * 16, 0, 0);
         }
       }
     }
